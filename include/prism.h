@@ -1,0 +1,213 @@
+/*
+ * prism.h -- C ABI of the MI355X PRISM / multislice STEM simulation library.
+ *
+ * The operations follow the statement of the method in Pryor, Ophus and Miao,
+ * "A Streaming Multi-GPU Implementation of Image Simulation Algorithms for
+ * Scanning Transmission Electron Microscopy" (2017):
+ *   - projected potential slices   ("Calculation of the Projected Potentials", Fig. 1a-b)
+ *   - compact S-matrix build       (Fig. 1f-h, Eqs. 1-2, "PRISM Probe Simulations")
+ *   - PRISM probe outputs          (Fig. 1i-k, "PRISM Probe Simulations")
+ *   - multislice probe outputs     (Fig. 1c-e, Eqs. 1-2, "Multislice Probe Simulations")
+ *
+ * Conventions common to every entry point
+ *   - Units: lengths in Angstrom, energies in eV, angles in rad, potentials
+ *     projected over a slice in V*A.
+ *   - Grids are square: n x n pixels over an Lx = Ly = L cell, pixel pitch
+ *     L/n, n a power of two in [64, 2048].  Arrays are row-major [y][x].
+ *   - Complex values are interleaved float pairs (re, im) ("complex64").
+ *   - Every function returns PRISM_OK (0) or a negative PRISM_E_* code and
+ *     then sets a thread-local message readable with prism_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Ownership: the caller owns every buffer and the HIP stream.  Pointers
+ *     documented as "device" must be device memory of the current HIP device;
+ *     pointers documented as "host" are read during the call only.  The
+ *     library allocates no device memory: scratch space comes in through a
+ *     caller-provided workspace whose size the *_plan / *_workspace call
+ *     reports.  `stream` is a hipStream_t (NULL = the default stream).
+ *   - Execution: work is queued on `stream` and the call returns without
+ *     waiting for it, except where a function says it uploads host tables:
+ *     those calls copy small host-computed tables into the workspace and wait
+ *     for that copy on `stream` before queuing kernels.
+ */
+#ifndef PRISM_H
+#define PRISM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PRISM_OK              0
+#define PRISM_E_INVAL        -1   /* argument out of its documented range, NULL pointer */
+#define PRISM_E_UNSUPPORTED  -2   /* valid physics, but a size this library does not build */
+#define PRISM_E_NOMEM        -3   /* host allocation failed */
+#define PRISM_E_DEVICE       -4   /* a HIP runtime call or kernel launch failed */
+#define PRISM_E_WORKSPACE    -5   /* workspace pointer NULL or smaller than required */
+
+/* ---- arithmetic of the beam contraction (probe synthesis) -------------- */
+#define PRISM_FP32           0    /* FP32 products, FP32 accumulation                   */
+#define PRISM_SPLIT_BF16X3   1    /* hi*hi + hi*lo + lo*hi BF16 MFMA, FP32 accumulation */
+#define PRISM_BF16           2    /* hi*hi BF16 MFMA, FP32 accumulation (error reported) */
+
+/* ---- structures -------------------------------------------------------- */
+typedef struct prism_atom {
+    double x, y, z;          /* position in A; x, y are wrapped into the cell */
+    int32_t species;         /* index into the species table                   */
+    int32_t pad;
+} prism_atom;
+
+/* Projected potential of one species as a sum of 2D Gaussians:
+ * V(r) = sum_i amp[i] / (2 pi width[i]^2) exp(-r^2 / (2 width[i]^2)),
+ * truncated at r < 6 max_i width[i].  amp = 2D integral (V*A^2), width = std-dev (A). */
+typedef struct prism_species {
+    int32_t n_gauss;         /* 1..4 */
+    int32_t pad;
+    double amp[4];
+    double width[4];
+} prism_species;
+
+/* Simulation grid: the cell is cut into n_slices = ceil(Lz/dz) slabs along z. */
+typedef struct prism_grid {
+    int32_t n;               /* pixels per side */
+    int32_t n_slices;        /* filled by prism_grid_init */
+    double cell[3];          /* Lx, Ly, Lz (A); Lx must equal Ly */
+    double dz;               /* slice thickness (A) */
+} prism_grid;
+
+/* Compact S-matrix geometry.  Inputs: grid, E0, alpha_max, f.  The rest is
+ * filled by prism_smatrix_plan. */
+typedef struct prism_smatrix_desc {
+    prism_grid grid;
+    double E0;               /* beam energy (eV) */
+    double alpha_max;        /* largest beam angle = probe semi-angle (rad) */
+    int32_t f;               /* interpolation factor: every f-th plane wave per axis */
+    int32_t n_beams;         /* |B_f| */
+    double lambda;           /* relativistic wavelength (A) */
+    double sigma;            /* interaction constant (rad / (V*A)) */
+    double alpha_aa;         /* anti-aliasing angle lambda*n/(4L) (rad) */
+    int32_t ns;              /* S-matrix side n/2 */
+    int32_t m_win;           /* probe window side ns/f */
+    size_t smatrix_bytes;    /* n_beams * ns * ns * 8 */
+    size_t build_ws_bytes;   /* workspace of prism_build_smatrix */
+} prism_smatrix_desc;
+
+/* Probe-synthesis plan (host side of a plan whose tables live in device memory). */
+typedef struct prism_probe_plan {
+    int64_t n_probes;
+    int32_t n_bins;          /* detector bins (3D output depth) */
+    int32_t n_tiles;         /* S-grid pixel tiles touched by at least one window */
+    int64_t n_entries;       /* (tile, probe) pairs */
+    int32_t max_per_tile;    /* largest probe count of one tile */
+    int32_t n_binned;        /* window pixels that fall in a detector bin */
+    double dalpha;           /* bin width (rad) */
+    size_t plan_bytes;       /* device bytes of the plan tables */
+    size_t ws_bytes;         /* workspace of prism_probe_outputs for all probes at once */
+    size_t off[8];           /* internal: offsets of the tables inside the plan buffer */
+} prism_probe_plan;
+
+/* ---- grid ---------------------------------------------------------------- */
+
+/* Validate a grid and fill n_slices = ceil(Lz/dz).
+ * Errors: PRISM_E_INVAL (n <= 0, dz <= 0, cell <= 0, NULL), PRISM_E_UNSUPPORTED
+ * (Lx != Ly, n not a power of two in [64, 2048]). */
+int prism_grid_init(const double cell[3], double dz, int32_t n, prism_grid* out);
+
+/* ---- projected potential ("Calculation of the Projected Potentials") ------ */
+
+/* Workspace bytes for prism_project_potential with n_atoms atoms. */
+int prism_project_potential_workspace(int64_t n_atoms, size_t* bytes);
+
+/* V[s][y][x] (device, float32, n_slices*n*n) = sum over atoms whose slab is s
+ * (s = clamp(floor(z/dz), 0, n_slices-1)) of their Gaussian terms at the
+ * minimum-image distance.  atoms, species: host arrays.  Uploads host tables.
+ * Errors: PRISM_E_INVAL (bad species index, n_gauss outside 1..4, width <= 0,
+ * cutoff 6*max(width) not below L/2), PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
+int prism_project_potential(const prism_atom* atoms, int64_t n_atoms,
+                            const prism_species* species, int32_t n_species,
+                            const prism_grid* grid, float* V,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* ---- compact S-matrix (Fig. 1g-h, Eqs. 1-2) ------------------------------- */
+
+/* Fill the derived fields of *d: lambda, sigma, alpha_aa, beams B_f = every
+ * f-th Fourier index (kx, ky) per axis with lambda*sqrt(kx^2+ky^2)/L <= alpha_max,
+ * ns = n/2, m_win = ns/f, and the byte sizes.
+ * Errors: PRISM_E_INVAL (E0 <= 0, alpha_max <= 0, f < 1), PRISM_E_UNSUPPORTED
+ * (alpha_max >= alpha_aa, f not dividing ns, m_win outside [16, 128]). */
+int prism_smatrix_plan(prism_smatrix_desc* d);
+
+/* Copy the beam list (kx, ky pairs, host int32 [cap][2]) in the order of the
+ * S-matrix layers.  Errors: PRISM_E_INVAL when cap < n_beams. */
+int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap);
+
+/* Build S[b][my][mx] (device complex64, n_beams*ns*ns): plane wave
+ * exp(2 pi i (kx x + ky y)/n) of beam b, transmitted by exp(i sigma V_s)
+ * (Eq. 1) and propagated by the band-limited Fresnel propagator
+ * [|q| < 1/(4 dx)] exp(-i pi lambda |q|^2 dz) (Eq. 2) through every slice,
+ * stored in real space on every second pixel (exact by the band limit).
+ * V: device float32 [n_slices][n][n].  Uploads host tables.
+ * Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE (ws_bytes < d->build_ws_bytes),
+ * PRISM_E_DEVICE. */
+int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* ---- PRISM probe outputs (Fig. 1i-k) -------------------------------------- */
+
+/* Plan the synthesis of n_probes probes at probe_xy (host float64 [n][2], A):
+ * window centres (nearest S-grid pixel), the (pixel tile, probe) cover lists,
+ * and the detector bin tables.  dalpha: bin width (rad); n_bins <= 0 selects
+ * ceil(alpha_aa / dalpha).  Fills *plan (sizes) only. */
+int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes,
+                          double dalpha, int32_t n_bins, prism_probe_plan* plan);
+
+/* Compute the plan tables and upload them into plan_dev (device, plan->plan_bytes).
+ * Uploads host tables (waits for the copy on `stream`). */
+int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
+                            const prism_probe_plan* plan, void* plan_dev, void* stream);
+
+/* out[p][bin] (device float32 [n_probes][n_bins]) = sum over the bin's window
+ * pixels of |FFT_M(psi_p)|^2 / M^4, where
+ * psi_p[v][u] = sum_b c_b(p) S_b[(cy - M/2 + v) mod ns][(cx - M/2 + u) mod ns],
+ * c_b(p) = |B_f|^(-1/2) exp(-2 pi i (kx_b x_p + ky_b y_p)/L).
+ * precision: PRISM_FP32, PRISM_SPLIT_BF16X3 or PRISM_BF16.  Fully asynchronous.
+ * Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE (ws_bytes < plan->ws_bytes), PRISM_E_DEVICE. */
+int prism_probe_outputs(const prism_smatrix_desc* d, const void* S,
+                        const prism_probe_plan* plan, const void* plan_dev,
+                        int32_t precision, float* out,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* ---- multislice probe outputs (Fig. 1c-e) --------------------------------- */
+
+/* Workspace bytes for multislice_outputs over n_probes probes processed
+ * `batch` at a time. */
+int multislice_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes, size_t* bytes);
+
+/* out[p][bin] (device float32 [n_probes][n_bins]): hard-aperture probe
+ * (lambda |q| <= alpha_max) with coefficients |B_1|^(-1/2) exp(-2 pi i q.r_p),
+ * transmitted and propagated through every slice (Eqs. 1-2), then
+ * |Psi(q)|^2 / n^4 summed over annular bins of width dalpha up to alpha_aa.
+ * probe_xy: host float64 [n_probes][2].  V: device float32 [n_slices][n][n].
+ * The probes are processed `batch` at a time inside ws.  Uploads host tables.
+ * Errors: PRISM_E_INVAL, PRISM_E_UNSUPPORTED, PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
+int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const float* V,
+                       const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins,
+                       int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- detector geometry ------------------------------------------------------ */
+
+/* map[ky][kx] (host int32 [m][m], FFT order) = floor(alpha / dalpha) with
+ * alpha = lambda * sqrt(kx^2 + ky^2) / Lw, or -1 when alpha >= alpha_aa or the
+ * bin is >= n_bins.  Every step is a correctly rounded float64 operation. */
+int prism_detector_bin_map(double lambda, double Lw, double alpha_aa, double dalpha,
+                           int32_t n_bins, int32_t m, int32_t* map);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* prism_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRISM_H */

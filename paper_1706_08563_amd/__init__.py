@@ -1,0 +1,17 @@
+"""MI355X (gfx950) PRISM / multislice STEM simulation.
+
+Thin Python layer over libprism.so (HIP kernels + C ABI, include/prism.h).
+PyTorch only provides device memory and the HIP stream; every step of the
+simulation runs in the library's kernels.  Importing this package fails if
+the library has not been built.
+"""
+from ._lib import (  # noqa: F401
+    PRISM_OK, PRISM_E_INVAL, PRISM_E_UNSUPPORTED, PRISM_E_NOMEM, PRISM_E_DEVICE, PRISM_E_WORKSPACE,
+    PRISM_FP32, PRISM_SPLIT_BF16X3, PRISM_BF16, PrismError, EXPORTED, LIB_PATH,
+    prism_atom, prism_species, prism_grid, prism_smatrix_desc, prism_probe_plan,
+)
+from .api import (  # noqa: F401
+    lib, prism_grid_init, prism_smatrix_plan, prism_beam_list, prism_detector_bin_map,
+    prism_project_potential, prism_build_smatrix, prism_probe_plan_init, prism_probe_plan_upload,
+    prism_probe_outputs, multislice_outputs, ProbePlan,
+)

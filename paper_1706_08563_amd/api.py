@@ -1,0 +1,166 @@
+"""Python entry points with the names of the C ABI (include/prism.h).
+
+Marshalling only: numpy host arrays become ctypes arrays, device buffers and
+workspaces are torch tensors on the current HIP device, and the current torch
+stream is handed to the library.  No step of the simulation is computed here.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._lib import (lib, check, prism_atom, prism_species, prism_grid, prism_smatrix_desc, prism_probe_plan,
+                   PRISM_FP32)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes, device=None):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
+
+
+# ---------------------------------------------------------------- grid --
+def prism_grid_init(cell, dz: float, n: int) -> prism_grid:
+    g = prism_grid()
+    c = (ctypes.c_double * 3)(*[float(v) for v in cell])
+    check(lib.prism_grid_init(c, float(dz), int(n), ctypes.byref(g)))
+    return g
+
+
+# ------------------------------------------------------------ S-matrix --
+def prism_smatrix_plan(grid: prism_grid, E0: float, alpha_max: float, f: int) -> prism_smatrix_desc:
+    d = prism_smatrix_desc()
+    d.grid = grid
+    d.E0 = float(E0)
+    d.alpha_max = float(alpha_max)
+    d.f = int(f)
+    check(lib.prism_smatrix_plan(ctypes.byref(d)))
+    return d
+
+
+def prism_beam_list(d: prism_smatrix_desc) -> np.ndarray:
+    out = np.zeros((d.n_beams, 2), dtype=np.int32)
+    check(lib.prism_beam_list(ctypes.byref(d), out.ctypes.data_as(ctypes.c_void_p), d.n_beams))
+    return out
+
+
+def prism_detector_bin_map(lam: float, Lw: float, alpha_aa: float, dalpha: float, n_bins: int, m: int) -> np.ndarray:
+    out = np.zeros((m, m), dtype=np.int32)
+    check(lib.prism_detector_bin_map(float(lam), float(Lw), float(alpha_aa), float(dalpha), int(n_bins), int(m),
+                                     out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+# ------------------------------------------------------------ potential --
+def prism_project_potential(pos, species_idx, species, grid: prism_grid, device=None):
+    """V [n_slices, n, n] float32 on the device from host atoms."""
+    torch = _torch()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n_atoms = len(pos)
+    atoms = (prism_atom * max(n_atoms, 1))()
+    for i in range(n_atoms):
+        atoms[i].x, atoms[i].y, atoms[i].z = float(pos[i, 0]), float(pos[i, 1]), float(pos[i, 2])
+        atoms[i].species = int(species_idx[i])
+    sp = (prism_species * len(species))()
+    for i, s in enumerate(species):
+        sp[i].n_gauss = len(s.amp)
+        for g in range(len(s.amp)):
+            sp[i].amp[g] = float(s.amp[g])
+            sp[i].width[g] = float(s.width[g])
+    need = ctypes.c_size_t()
+    check(lib.prism_project_potential_workspace(n_atoms, ctypes.byref(need)))
+    ws = _workspace(need.value, device)
+    V = torch.empty((grid.n_slices, grid.n, grid.n), dtype=torch.float32, device=device or "cuda")
+    check(lib.prism_project_potential(atoms, n_atoms, sp, len(species), ctypes.byref(grid), _dev(V), _dev(ws),
+                                      need.value, _stream()))
+    return V
+
+
+def prism_build_smatrix(d: prism_smatrix_desc, V, ws=None):
+    """S [n_beams, n/2, n/2] complex64 on the device."""
+    torch = _torch()
+    S = torch.empty((d.n_beams, d.ns, d.ns), dtype=torch.complex64, device=V.device)
+    if ws is None:
+        ws = _workspace(d.build_ws_bytes, V.device)
+    check(lib.prism_build_smatrix(ctypes.byref(d), _dev(V), _dev(S), _dev(ws), ws.numel(), _stream()))
+    return S
+
+
+# -------------------------------------------------------- probe outputs --
+@dataclass
+class ProbePlan:
+    plan: prism_probe_plan
+    dev: object          # device tensor holding the plan tables
+    xy: np.ndarray       # host positions the plan was made for
+
+
+def prism_probe_plan_init(d: prism_smatrix_desc, xy, dalpha: float = 1e-3, n_bins: int = 0) -> prism_probe_plan:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    p = prism_probe_plan()
+    check(lib.prism_probe_plan_init(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha),
+                                    int(n_bins), ctypes.byref(p)))
+    return p
+
+
+def prism_probe_plan_upload(d: prism_smatrix_desc, xy, dalpha: float = 1e-3, n_bins: int = 0,
+                            device=None) -> ProbePlan:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    p = prism_probe_plan_init(d, xy, dalpha, n_bins)
+    dev = _workspace(p.plan_bytes, device)
+    check(lib.prism_probe_plan_upload(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p),
+                                      _dev(dev), _stream()))
+    return ProbePlan(p, dev, xy)
+
+
+def prism_probe_outputs(d: prism_smatrix_desc, S, plan: ProbePlan, precision: int = PRISM_FP32, ws=None, out=None):
+    """out [n_probes, n_bins] float32 on the device."""
+    torch = _torch()
+    p = plan.plan
+    if out is None:
+        out = torch.empty((p.n_probes, p.n_bins), dtype=torch.float32, device=S.device)
+    if ws is None:
+        ws = _workspace(p.ws_bytes, S.device)
+    check(lib.prism_probe_outputs(ctypes.byref(d), _dev(S), ctypes.byref(p), _dev(plan.dev), int(precision),
+                                  _dev(out), _dev(ws), ws.numel(), _stream()))
+    return out
+
+
+# ------------------------------------------------------------ multislice --
+def multislice_workspace(grid: prism_grid, batch: int, n_probes: int) -> int:
+    need = ctypes.c_size_t()
+    check(lib.multislice_workspace(ctypes.byref(grid), int(batch), int(n_probes), ctypes.byref(need)))
+    return need.value
+
+
+def multislice_outputs(grid: prism_grid, E0: float, alpha_max: float, V, xy, dalpha: float = 1e-3,
+                       n_bins: int = 0, batch: int = 64, ws=None, out=None):
+    """out [n_probes, n_bins] float32 on the device."""
+    torch = _torch()
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    if n_bins <= 0:
+        # alpha_AA depends on the grid only; any legal interpolation factor reports it
+        f = max(1, (grid.n // 2) // 128)
+        n_bins = int(np.ceil(prism_smatrix_plan(grid, E0, alpha_max, f).alpha_aa / dalpha))
+    if ws is None:
+        ws = _workspace(multislice_workspace(grid, batch, len(xy)), V.device)
+    if out is None:
+        out = torch.empty((len(xy), n_bins), dtype=torch.float32, device=V.device)
+    check(lib.multislice_outputs(ctypes.byref(grid), float(E0), float(alpha_max), _dev(V),
+                                 xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha), int(n_bins), int(batch),
+                                 _dev(out), _dev(ws), ws.numel(), _stream()))
+    return out

@@ -1,0 +1,688 @@
+// api.hip -- C ABI of the PRISM / multislice library: validation, host
+// planning (FP64, integer), table uploads and kernel dispatch.
+//
+// Floating-point decisions that pick integers (beam membership, aperture,
+// detector bins, window centres) are explicit sequences of correctly rounded
+// IEEE-754 float64 operations, evaluated without contraction, so that any
+// conforming implementation of the same expressions reproduces them exactly.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "prism.h"
+
+using namespace prism;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(PRISM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- physics --
+// Relativistic wavelength and interaction constant of Eqs. (1)-(2), CODATA 2018.
+constexpr double kPlanck = 6.62607015e-34, kLight = 299792458.0, kCharge = 1.602176634e-19,
+                 kMass0 = 9.1093837015e-31;
+constexpr double kPi = 3.14159265358979323846;
+
+double wavelength_A(double E0) {
+    double eE = kCharge * E0;
+    return kPlanck * kLight / std::sqrt(eE * (2.0 * kMass0 * kLight * kLight + eE)) * 1e10;
+}
+double sigma_per_VA(double E0) {
+    double lam_m = wavelength_A(E0) * 1e-10;
+    double m = kMass0 + kCharge * E0 / (kLight * kLight);
+    return 2.0 * kPi * m * kCharge * lam_m / (kPlanck * kPlanck) * 1e-10;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// FFT-order integer frequency of index i on an m-point grid.
+inline int freq(int i, int m) { return i < (m + 1) / 2 ? i : i - m; }
+// band column j (of n/2) -> kx in [-n/4, n/4)
+inline int band_k(int j, int n) { return j < n / 4 ? j : j - n / 2; }
+
+// lambda * sqrt(kx^2 + ky^2) / Lw  (the one expression every angle test uses)
+inline double angle_of(double lam, int kx, int ky, double Lw) {
+    return lam * std::sqrt((double)(kx * kx + ky * ky)) / Lw;
+}
+inline double alpha_aa_of(double lam, int n, double L) { return lam * (double)n / (4.0 * L); }
+inline int bin_of(double lam, int kx, int ky, double Lw, double a_aa, double dalpha, int n_bins) {
+    double a = angle_of(lam, kx, ky, Lw);
+    if (!(a < a_aa)) return -1;
+    double b = std::floor(a / dalpha);
+    if (b >= (double)n_bins) return -1;
+    return (int)b;
+}
+
+// Beams: every f-th Fourier index inside alpha_max, ordered by (ky, kx).
+std::vector<int2> beam_list(int n, double L, double lam, double alpha_max, int f) {
+    std::vector<int2> out;
+    for (int ky = -n / 2; ky < n / 2; ++ky)
+        for (int kx = -n / 2; kx < n / 2; ++kx) {
+            if (kx % f != 0 || ky % f != 0) continue;
+            if (angle_of(lam, kx, ky, L) <= alpha_max) out.push_back(make_int2(kx, ky));
+        }
+    return out;
+}
+
+// Window centre: nearest S-grid pixel (round half up), periodic.
+inline int centre_of(double x, double L, int n) {
+    double c = std::floor(x / (2.0 * (L / n)) + 0.5);
+    int ns = n / 2;
+    long long ci = (long long)c % ns;
+    if (ci < 0) ci += ns;
+    return (int)ci;
+}
+
+int default_bins(double a_aa, double dalpha) { return (int)std::ceil(a_aa / dalpha); }
+
+// ----------------------------------------------------- workspace carving --
+struct Carve {
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+std::vector<float2> twiddle_table(int m) {
+    std::vector<float2> t(m);
+    for (int i = 0; i < m; ++i) {
+        double a = 2.0 * kPi * (double)i / (double)m;
+        t[i] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    return t;
+}
+
+// Host-side tables of the propagation passes, laid out as one blob.
+struct PropHost {
+    std::vector<float2> tw_half, tw_full, band, prop;
+};
+
+PropHost prop_tables(int n, double L, double lam, double dz) {
+    PropHost h;
+    const int Lh = n / 2;
+    h.tw_half = twiddle_table(Lh);
+    h.tw_full = twiddle_table(n);
+    h.band.resize(Lh);
+    h.prop.resize(Lh);
+    for (int j = 0; j < Lh; ++j) {
+        int k = band_k(j, n);
+        double a = 2.0 * kPi * (double)k / (double)n;
+        h.band[j] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        // phase -pi * lam dz k^2 / L^2, reduced to (-pi, pi]
+        double t = lam * dz * (double)k * (double)k / (L * L);
+        t -= 2.0 * std::nearbyint(t / 2.0);
+        double ph = -kPi * t;
+        h.prop[j] = make_float2((float)(std::cos(ph) / n), (float)(std::sin(ph) / n));
+    }
+    return h;
+}
+
+struct PropDev {
+    float2 *tw_half, *tw_full, *band, *prop;
+    PropTables tables() const { return PropTables{tw_half, tw_full, band, prop}; }
+};
+
+PropDev carve_prop(Carve& c, int n) {
+    PropDev d;
+    d.tw_half = c.take<float2>(n / 2);
+    d.tw_full = c.take<float2>(n);
+    d.band = c.take<float2>(n / 2);
+    d.prop = c.take<float2>(n / 2);
+    return d;
+}
+
+// Copy a host vector into a blob at the device pointer's offset.
+template <class T>
+void stage(std::vector<char>& blob, const void* dev_base, const T* dev_ptr, const std::vector<T>& v) {
+    size_t off = reinterpret_cast<const char*>(dev_ptr) - static_cast<const char*>(dev_base);
+    if (blob.size() < off + v.size() * sizeof(T)) blob.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+int upload(void* dev, const std::vector<char>& blob, hipStream_t st) {
+    if (blob.empty()) return PRISM_OK;
+    HIP_TRY(hipMemcpyAsync(dev, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PRISM_OK;
+}
+
+int check_grid(const prism_grid* g) {
+    if (!g) return fail(PRISM_E_INVAL, "grid is NULL");
+    if (g->n <= 0 || !(g->dz > 0) || !(g->cell[0] > 0) || !(g->cell[1] > 0) || !(g->cell[2] > 0))
+        return fail(PRISM_E_INVAL, "grid: n, dz and cell must be positive");
+    if (g->cell[0] != g->cell[1]) return fail(PRISM_E_UNSUPPORTED, "grid: only square cells (Lx == Ly)");
+    if (!is_pow2(g->n) || g->n < 64 || g->n > 2048)
+        return fail(PRISM_E_UNSUPPORTED, "grid: n = %d must be a power of two in [64, 2048]", g->n);
+    int s = (int)std::ceil(g->cell[2] / g->dz - 1e-12);
+    if (g->n_slices != s) return fail(PRISM_E_INVAL, "grid: n_slices %d != ceil(Lz/dz) = %d", g->n_slices, s);
+    return PRISM_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+struct ProbeHost {
+    std::vector<double2> xy;
+    std::vector<int2> corner;
+    std::vector<int> tile_start, tile_probes, perm, bin_start;
+    std::vector<float2> tw_m;
+    std::vector<int2> beams;
+};
+
+// Detector tables: pixels (index ky_i * m + kx_i of an m x m FFT-order grid)
+// grouped by bin, ascending pixel index inside a bin.
+void bin_tables(double lam, double Lw, double a_aa, double dalpha, int n_bins, int m, std::vector<int>& perm,
+                std::vector<int>& start) {
+    std::vector<int> cnt(n_bins + 1, 0);
+    std::vector<int> bins((size_t)m * m);
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) {
+            int b = bin_of(lam, freq(c, m), freq(r, m), Lw, a_aa, dalpha, n_bins);
+            bins[(size_t)r * m + c] = b;
+            if (b >= 0) cnt[b + 1]++;
+        }
+    start.assign(n_bins + 1, 0);
+    for (int b = 0; b < n_bins; ++b) start[b + 1] = start[b] + cnt[b + 1];
+    perm.assign(start[n_bins], 0);
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int i = 0; i < m * m; ++i)
+        if (bins[i] >= 0) perm[fill[bins[i]]++] = i;
+}
+
+int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, double dalpha, int n_bins,
+               ProbeHost& h, int& max_per_tile) {
+    const int n = d->grid.n, ns = d->ns, M = d->m_win;
+    const double L = d->grid.cell[0];
+    const int ntx = ns / 16, n_tiles = ntx * ntx;
+    h.xy.resize(n_probes);
+    h.corner.resize(n_probes);
+    std::vector<int> count(n_tiles, 0);
+    std::vector<char> mark_x(ntx), mark_y(ntx);
+    auto cover = [&](int start, std::vector<char>& mark) {
+        std::fill(mark.begin(), mark.end(), 0);
+        for (int v = 0; v < M; v += 16) mark[((start + v) & (ns - 1)) / 16] = 1;
+        mark[((start + M - 1) & (ns - 1)) / 16] = 1;
+    };
+    for (int64_t p = 0; p < n_probes; ++p) {
+        double x = xy[2 * p], y = xy[2 * p + 1];
+        if (!std::isfinite(x) || !std::isfinite(y)) return fail(PRISM_E_INVAL, "probe %lld: non-finite position", (long long)p);
+        h.xy[p] = make_double2(x, y);
+        int cx = centre_of(x, L, n), cy = centre_of(y, L, n);
+        h.corner[p] = make_int2((cx - M / 2) & (ns - 1), (cy - M / 2) & (ns - 1));
+        cover(h.corner[p].x, mark_x);
+        cover(h.corner[p].y, mark_y);
+        for (int ty = 0; ty < ntx; ++ty)
+            if (mark_y[ty])
+                for (int tx = 0; tx < ntx; ++tx)
+                    if (mark_x[tx]) count[ty * ntx + tx]++;
+    }
+    h.tile_start.assign(n_tiles + 1, 0);
+    max_per_tile = 0;
+    for (int t = 0; t < n_tiles; ++t) {
+        h.tile_start[t + 1] = h.tile_start[t] + count[t];
+        max_per_tile = std::max(max_per_tile, count[t]);
+    }
+    h.tile_probes.assign(h.tile_start[n_tiles], 0);
+    std::vector<int> fill(h.tile_start.begin(), h.tile_start.end() - 1);
+    for (int64_t p = 0; p < n_probes; ++p) {
+        cover(h.corner[p].x, mark_x);
+        cover(h.corner[p].y, mark_y);
+        for (int ty = 0; ty < ntx; ++ty)
+            if (mark_y[ty])
+                for (int tx = 0; tx < ntx; ++tx)
+                    if (mark_x[tx]) h.tile_probes[fill[ty * ntx + tx]++] = (int)p;
+    }
+    bin_tables(d->lambda, L / d->f, d->alpha_aa, dalpha, n_bins, M, h.perm, h.bin_start);
+    h.tw_m = twiddle_table(M);
+    h.beams = beam_list(n, L, d->lambda, d->alpha_max, d->f);
+    return PRISM_OK;
+}
+
+int check_desc(const prism_smatrix_desc* d) {
+    if (!d) return fail(PRISM_E_INVAL, "descriptor is NULL");
+    prism_smatrix_desc c = *d;
+    int rc = prism_smatrix_plan(&c);
+    if (rc) return rc;
+    if (c.n_beams != d->n_beams || c.ns != d->ns || c.m_win != d->m_win)
+        return fail(PRISM_E_INVAL, "descriptor was not filled by prism_smatrix_plan");
+    return PRISM_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI ==
+extern "C" {
+
+const char* prism_last_error(void) { return g_err.c_str(); }
+
+int prism_grid_init(const double cell[3], double dz, int32_t n, prism_grid* out) {
+    if (!cell || !out) return fail(PRISM_E_INVAL, "NULL argument");
+    prism_grid g{};
+    g.n = n;
+    g.cell[0] = cell[0];
+    g.cell[1] = cell[1];
+    g.cell[2] = cell[2];
+    g.dz = dz;
+    g.n_slices = (dz > 0 && cell[2] > 0) ? (int)std::ceil(cell[2] / dz - 1e-12) : 0;
+    int rc = check_grid(&g);
+    if (rc) return rc;
+    *out = g;
+    return PRISM_OK;
+}
+
+int prism_detector_bin_map(double lambda, double Lw, double alpha_aa, double dalpha, int32_t n_bins, int32_t m,
+                           int32_t* map) {
+    if (!map || m <= 0 || !(lambda > 0) || !(Lw > 0) || !(dalpha > 0) || n_bins <= 0)
+        return fail(PRISM_E_INVAL, "bin map: invalid argument");
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) map[(size_t)r * m + c] = bin_of(lambda, freq(c, m), freq(r, m), Lw, alpha_aa, dalpha, n_bins);
+    return PRISM_OK;
+}
+
+// ------------------------------------------------------------ potential --
+int prism_project_potential_workspace(int64_t n_atoms, size_t* bytes) {
+    if (!bytes || n_atoms < 0) return fail(PRISM_E_INVAL, "invalid argument");
+    Carve c(nullptr);
+    c.take<PotAtom>((size_t)std::max<int64_t>(n_atoms, 1));
+    c.take<int>(8193);
+    c.take<PotSpecies>(256);
+    *bytes = c.off + 256;
+    return PRISM_OK;
+}
+
+int prism_project_potential(const prism_atom* atoms, int64_t n_atoms, const prism_species* species, int32_t n_species,
+                            const prism_grid* grid, float* V, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!V || (n_atoms > 0 && !atoms) || !species || n_species <= 0 || n_species > 256 || n_atoms < 0)
+        return fail(PRISM_E_INVAL, "potential: invalid argument");
+    if (grid->n_slices > 8192) return fail(PRISM_E_UNSUPPORTED, "potential: more than 8192 slices");
+    size_t need = 0;
+    prism_project_potential_workspace(n_atoms, &need);
+    if (!ws || ws_bytes < need) return fail(PRISM_E_WORKSPACE, "potential: workspace %zu < %zu bytes", ws_bytes, need);
+    const double L = grid->cell[0];
+    const int S = grid->n_slices;
+    std::vector<PotSpecies> sp(n_species);
+    float rc_max = 0.f;
+    for (int i = 0; i < n_species; ++i) {
+        const prism_species& s = species[i];
+        if (s.n_gauss < 1 || s.n_gauss > 4) return fail(PRISM_E_INVAL, "species %d: n_gauss must be 1..4", i);
+        double wmax = 0;
+        PotSpecies p{};
+        for (int g = 0; g < s.n_gauss; ++g) {
+            if (!(s.width[g] > 0)) return fail(PRISM_E_INVAL, "species %d: width must be positive", i);
+            wmax = std::max(wmax, s.width[g]);
+            p.amp_n[g] = (float)(s.amp[g] / (2.0 * kPi * s.width[g] * s.width[g]));
+            p.inv2w2[g] = (float)(1.0 / (2.0 * s.width[g] * s.width[g]));
+        }
+        double rcut = 6.0 * wmax;
+        if (!(2.0 * rcut < L)) return fail(PRISM_E_INVAL, "species %d: cutoff 6*max(width) must be below L/2", i);
+        p.n_gauss = s.n_gauss;
+        p.rc = (float)rcut;
+        p.rc2 = (float)(rcut * rcut);
+        rc_max = std::max(rc_max, p.rc);
+        sp[i] = p;
+    }
+    // atoms sorted (stably) by slice
+    std::vector<int> slice_of(n_atoms);
+    std::vector<int> start(S + 1, 0);
+    for (int64_t a = 0; a < n_atoms; ++a) {
+        const prism_atom& at = atoms[a];
+        if (at.species < 0 || at.species >= n_species) return fail(PRISM_E_INVAL, "atom %lld: bad species", (long long)a);
+        if (!std::isfinite(at.x) || !std::isfinite(at.y) || !std::isfinite(at.z))
+            return fail(PRISM_E_INVAL, "atom %lld: non-finite position", (long long)a);
+        double s = std::floor(at.z / grid->dz);
+        int si = s < 0 ? 0 : (s > S - 1 ? S - 1 : (int)s);
+        slice_of[a] = si;
+        start[si + 1]++;
+    }
+    for (int s = 0; s < S; ++s) start[s + 1] += start[s];
+    std::vector<PotAtom> sorted(std::max<int64_t>(n_atoms, 1));
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int64_t a = 0; a < n_atoms; ++a) {
+        double x = std::fmod(atoms[a].x, L), y = std::fmod(atoms[a].y, L);
+        if (x < 0) x += L;
+        if (y < 0) y += L;
+        sorted[fill[slice_of[a]]++] = PotAtom{x, y, slice_of[a], atoms[a].species};
+    }
+    Carve c(ws);
+    PotAtom* d_atoms = c.take<PotAtom>(sorted.size());
+    int* d_start = c.take<int>(8193);
+    PotSpecies* d_sp = c.take<PotSpecies>(256);
+    std::vector<char> blob;
+    stage(blob, ws, d_atoms, sorted);
+    stage(blob, ws, d_start, start);
+    stage(blob, ws, d_sp, sp);
+    hipStream_t st = as_stream(stream);
+    rc = upload(ws, blob, st);
+    if (rc) return rc;
+    HIP_TRY(launch_potential(V, grid->n, S, L, d_atoms, d_start, d_sp, rc_max, st));
+    return PRISM_OK;
+}
+
+// ------------------------------------------------------------- S-matrix --
+int prism_smatrix_plan(prism_smatrix_desc* d) {
+    if (!d) return fail(PRISM_E_INVAL, "descriptor is NULL");
+    int rc = check_grid(&d->grid);
+    if (rc) return rc;
+    if (!(d->E0 > 0) || !(d->alpha_max > 0) || d->f < 1)
+        return fail(PRISM_E_INVAL, "smatrix: E0, alpha_max must be positive and f >= 1");
+    const int n = d->grid.n;
+    const double L = d->grid.cell[0];
+    d->lambda = wavelength_A(d->E0);
+    d->sigma = sigma_per_VA(d->E0);
+    d->alpha_aa = alpha_aa_of(d->lambda, n, L);
+    if (!(d->alpha_max < d->alpha_aa))
+        return fail(PRISM_E_UNSUPPORTED, "smatrix: alpha_max %.6g must be below alpha_AA %.6g", d->alpha_max,
+                    d->alpha_aa);
+    d->ns = n / 2;
+    if (d->ns % d->f != 0) return fail(PRISM_E_UNSUPPORTED, "smatrix: f = %d must divide n/2 = %d", d->f, d->ns);
+    d->m_win = d->ns / d->f;
+    if (d->m_win < 16 || d->m_win > 128)
+        return fail(PRISM_E_UNSUPPORTED, "smatrix: window side n/(2f) = %d outside [16, 128]", d->m_win);
+    d->n_beams = (int32_t)beam_list(n, L, d->lambda, d->alpha_max, d->f).size();
+    d->smatrix_bytes = (size_t)d->n_beams * d->ns * d->ns * sizeof(float2);
+    Carve c(nullptr);
+    carve_prop(c, n);
+    c.take<int2>(d->n_beams);
+    c.take<float2>((size_t)d->grid.n_slices * n * n);
+    c.take<float2>((size_t)d->n_beams * (n / 2) * n);
+    d->build_ws_bytes = c.off + 256;
+    return PRISM_OK;
+}
+
+int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    if (!k_out || cap < d->n_beams) return fail(PRISM_E_INVAL, "beam list: capacity %d < %d", cap, d->n_beams);
+    auto b = beam_list(d->grid.n, d->grid.cell[0], d->lambda, d->alpha_max, d->f);
+    for (size_t i = 0; i < b.size(); ++i) {
+        k_out[2 * i] = b[i].x;
+        k_out[2 * i + 1] = b[i].y;
+    }
+    return PRISM_OK;
+}
+
+int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, void* ws, size_t ws_bytes,
+                        void* stream) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    if (!V || !S) return fail(PRISM_E_INVAL, "build: NULL V or S");
+    if (!ws || ws_bytes < d->build_ws_bytes)
+        return fail(PRISM_E_WORKSPACE, "build: workspace %zu < %zu bytes", ws_bytes, d->build_ws_bytes);
+    const int n = d->grid.n, B = d->n_beams, nsl = d->grid.n_slices;
+    const double L = d->grid.cell[0];
+    hipStream_t st = as_stream(stream);
+    Carve c(ws);
+    PropDev pd = carve_prop(c, n);
+    int2* d_beams = c.take<int2>(B);
+    float2* T = c.take<float2>((size_t)nsl * n * n);
+    float2* W = c.take<float2>((size_t)B * (n / 2) * n);
+    PropHost ph = prop_tables(n, L, d->lambda, d->grid.dz);
+    std::vector<char> blob;
+    stage(blob, ws, pd.tw_half, ph.tw_half);
+    stage(blob, ws, pd.tw_full, ph.tw_full);
+    stage(blob, ws, pd.band, ph.band);
+    stage(blob, ws, pd.prop, ph.prop);
+    stage(blob, ws, d_beams, beam_list(n, L, d->lambda, d->alpha_max, d->f));
+    rc = upload(ws, blob, st);
+    if (rc) return rc;
+    const PropTables tb = pd.tables();
+    HIP_TRY(launch_transmission(V, T, (int64_t)nsl * n * n, (float)d->sigma, st));
+    for (int s = 0; s < nsl; ++s) {
+        HIP_TRY(launch_pass_a(n, W, T + (size_t)s * n * n, tb, d_beams, s == 0, B, st));
+        HIP_TRY(launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, W, tb, nullptr, nullptr, nullptr, nullptr,
+                              0.0, 0.f, B, st));
+    }
+    HIP_TRY(launch_smatrix_final(n, W, static_cast<float2*>(S), pd.tw_half, B, st));
+    return PRISM_OK;
+}
+
+// -------------------------------------------------------- probe outputs --
+int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes, double dalpha,
+                          int32_t n_bins, prism_probe_plan* plan) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    if (!plan || (n_probes > 0 && !probe_xy) || n_probes < 0 || n_probes > (1 << 30) || !(dalpha > 0))
+        return fail(PRISM_E_INVAL, "probe plan: invalid argument");
+    if (n_bins <= 0) n_bins = default_bins(d->alpha_aa, dalpha);
+    ProbeHost h;
+    int maxpt = 0;
+    rc = probe_host(d, probe_xy, n_probes, dalpha, n_bins, h, maxpt);
+    if (rc) return rc;
+    prism_probe_plan p{};
+    p.n_probes = n_probes;
+    p.n_bins = n_bins;
+    p.n_tiles = (int32_t)(h.tile_start.size() - 1);
+    p.n_entries = (int64_t)h.tile_probes.size();
+    p.max_per_tile = maxpt;
+    p.n_binned = (int32_t)h.perm.size();
+    p.dalpha = dalpha;
+    Carve c(nullptr);
+    const size_t P = (size_t)std::max<int64_t>(n_probes, 1);
+    p.off[0] = (size_t)c.take<double2>(P);
+    p.off[1] = (size_t)c.take<int2>(P);
+    p.off[2] = (size_t)c.take<int>(h.tile_start.size());
+    p.off[3] = (size_t)c.take<int>(std::max<size_t>(h.tile_probes.size(), 1));
+    p.off[4] = (size_t)c.take<int>(std::max<size_t>(h.perm.size(), 1));
+    p.off[5] = (size_t)c.take<int>(h.bin_start.size());
+    p.off[6] = (size_t)c.take<float2>(h.tw_m.size());
+    p.off[7] = (size_t)c.take<int2>(h.beams.size());
+    p.plan_bytes = c.off + 256;
+    Carve w(nullptr);
+    w.take<float2>(P * d->n_beams);
+    w.take<float2>(P * d->m_win * d->m_win);
+    p.ws_bytes = w.off + 256;
+    *plan = p;
+    return PRISM_OK;
+}
+
+int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy, const prism_probe_plan* plan,
+                            void* plan_dev, void* stream) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    if (!plan || !plan_dev) return fail(PRISM_E_INVAL, "probe plan upload: NULL argument");
+    ProbeHost h;
+    int maxpt = 0;
+    rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, h, maxpt);
+    if (rc) return rc;
+    if ((int64_t)h.tile_probes.size() != plan->n_entries || (int)h.perm.size() != plan->n_binned)
+        return fail(PRISM_E_INVAL, "probe plan upload: plan does not match these probes");
+    std::vector<char> blob(plan->plan_bytes, 0);
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(blob.data() + off, src, bytes);
+    };
+    put(plan->off[0], h.xy.data(), h.xy.size() * sizeof(double2));
+    put(plan->off[1], h.corner.data(), h.corner.size() * sizeof(int2));
+    put(plan->off[2], h.tile_start.data(), h.tile_start.size() * sizeof(int));
+    put(plan->off[3], h.tile_probes.data(), h.tile_probes.size() * sizeof(int));
+    put(plan->off[4], h.perm.data(), h.perm.size() * sizeof(int));
+    put(plan->off[5], h.bin_start.data(), h.bin_start.size() * sizeof(int));
+    put(plan->off[6], h.tw_m.data(), h.tw_m.size() * sizeof(float2));
+    put(plan->off[7], h.beams.data(), h.beams.size() * sizeof(int2));
+    return upload(plan_dev, blob, as_stream(stream));
+}
+
+int prism_probe_outputs(const prism_smatrix_desc* d, const void* S, const prism_probe_plan* plan,
+                        const void* plan_dev, int32_t precision, float* out, void* ws, size_t ws_bytes,
+                        void* stream) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    if (!S || !plan || !plan_dev || !out) return fail(PRISM_E_INVAL, "probe outputs: NULL argument");
+    if (precision != PRISM_FP32 && precision != PRISM_SPLIT_BF16X3 && precision != PRISM_BF16)
+        return fail(PRISM_E_INVAL, "probe outputs: unknown precision %d", precision);
+    if (!ws || ws_bytes < plan->ws_bytes)
+        return fail(PRISM_E_WORKSPACE, "probe outputs: workspace %zu < %zu bytes", ws_bytes, plan->ws_bytes);
+    if (plan->n_probes == 0) return PRISM_OK;
+    const char* pb = static_cast<const char*>(plan_dev);
+    auto xy = reinterpret_cast<const double2*>(pb + plan->off[0]);
+    auto corner = reinterpret_cast<const int2*>(pb + plan->off[1]);
+    auto tstart = reinterpret_cast<const int*>(pb + plan->off[2]);
+    auto tprobes = reinterpret_cast<const int*>(pb + plan->off[3]);
+    auto perm = reinterpret_cast<const int*>(pb + plan->off[4]);
+    auto bstart = reinterpret_cast<const int*>(pb + plan->off[5]);
+    auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
+    auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
+    const int P = (int)plan->n_probes, B = d->n_beams, M = d->m_win;
+    Carve c(ws);
+    float2* C = c.take<float2>((size_t)P * B);
+    float2* win = c.take<float2>((size_t)P * M * M);
+    hipStream_t st = as_stream(stream);
+    HIP_TRY(launch_coefficients(C, xy, beams, P, B, 1.0 / d->grid.cell[0], (float)(1.0 / std::sqrt((double)B)), st));
+    HIP_TRY(launch_contract(precision, C, static_cast<const float2*>(S), win, tstart, tprobes, corner, plan->n_tiles,
+                            plan->max_per_tile, B, d->ns, M, st));
+    HIP_TRY(launch_window_detect(M, win, out, perm, bstart, tw_m, P, plan->n_bins, st));
+    return PRISM_OK;
+}
+
+// ------------------------------------------------------------ multislice --
+static void multislice_carve(Carve& c, int n, int nsl, int64_t n_probes, int batch, int n_bins, size_t n_binned,
+                             PropDev& pd, int*& kymax, int*& perm, int*& bstart, double2*& xy, float2*& T,
+                             float2*& W, float*& I) {
+    pd = carve_prop(c, n);
+    kymax = c.take<int>(n / 2);
+    perm = c.take<int>(std::max<size_t>(n_binned, 1));
+    bstart = c.take<int>(n_bins + 1);
+    xy = c.take<double2>((size_t)std::max<int64_t>(n_probes, 1));
+    T = c.take<float2>((size_t)nsl * n * n);
+    W = c.take<float2>((size_t)batch * (n / 2) * n);
+    I = c.take<float>((size_t)batch * (n / 2) * (n / 2));
+}
+
+int multislice_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes, size_t* bytes) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!bytes || batch < 1 || n_probes < 0) return fail(PRISM_E_INVAL, "multislice workspace: invalid argument");
+    const int n = grid->n;
+    Carve c(nullptr);
+    PropDev pd;
+    int *a, *b, *e;
+    double2* xy;
+    float2 *T, *W;
+    float* I;
+    // bins can cover at most the (n/2)^2 band pixels
+    multislice_carve(c, n, grid->n_slices, n_probes, batch, 4096, (size_t)(n / 2) * (n / 2), pd, a, b, e, xy, T, W, I);
+    *bytes = c.off + 256;
+    return PRISM_OK;
+}
+
+int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const float* V, const double* probe_xy,
+                       int64_t n_probes, double dalpha, int32_t n_bins, int32_t batch, float* out, void* ws,
+                       size_t ws_bytes, void* stream) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!V || !out || (n_probes > 0 && !probe_xy) || n_probes < 0 || batch < 1 || !(E0 > 0) || !(alpha_max > 0) ||
+        !(dalpha > 0))
+        return fail(PRISM_E_INVAL, "multislice: invalid argument");
+    const int n = grid->n, Lh = n / 2, nsl = grid->n_slices;
+    const double L = grid->cell[0];
+    const double lam = wavelength_A(E0), sig = sigma_per_VA(E0), a_aa = alpha_aa_of(lam, n, L);
+    if (!(alpha_max < a_aa))
+        return fail(PRISM_E_UNSUPPORTED, "multislice: alpha_max %.6g must be below alpha_AA %.6g", alpha_max, a_aa);
+    if (n_bins <= 0) n_bins = default_bins(a_aa, dalpha);
+    if (n_bins > 4096) return fail(PRISM_E_UNSUPPORTED, "multislice: more than 4096 bins");
+    size_t need = 0;
+    rc = multislice_workspace(grid, batch, n_probes, &need);
+    if (rc) return rc;
+    if (!ws || ws_bytes < need) return fail(PRISM_E_WORKSPACE, "multislice: workspace %zu < %zu bytes", ws_bytes, need);
+    // aperture per band column and its size
+    std::vector<int> kymax(Lh, -1);
+    long long n_ap = 0;
+    for (int j = 0; j < Lh; ++j) {
+        int kx = band_k(j, n);
+        int m = -1;
+        while (m + 1 < n / 4 && angle_of(lam, kx, m + 1, L) <= alpha_max) ++m;
+        kymax[j] = m;
+        if (m >= 0) n_ap += 2 * m + 1;
+    }
+    if (n_ap == 0) return fail(PRISM_E_INVAL, "multislice: empty aperture");
+    // bins over band pixels, index j * (n/2) + j' (kx from j, ky from j')
+    std::vector<int> cnt(n_bins + 1, 0), bins((size_t)Lh * Lh);
+    for (int j = 0; j < Lh; ++j)
+        for (int jp = 0; jp < Lh; ++jp) {
+            int b = bin_of(lam, band_k(j, n), band_k(jp, n), L, a_aa, dalpha, n_bins);
+            bins[(size_t)j * Lh + jp] = b;
+            if (b >= 0) cnt[b + 1]++;
+        }
+    std::vector<int> bstart(n_bins + 1, 0);
+    for (int b = 0; b < n_bins; ++b) bstart[b + 1] = bstart[b] + cnt[b + 1];
+    std::vector<int> perm(bstart[n_bins]);
+    {
+        std::vector<int> fill(bstart.begin(), bstart.end() - 1);
+        for (size_t i = 0; i < bins.size(); ++i)
+            if (bins[i] >= 0) perm[fill[bins[i]]++] = (int)i;
+    }
+    std::vector<double2> xy(std::max<int64_t>(n_probes, 1));
+    for (int64_t p = 0; p < n_probes; ++p) {
+        if (!std::isfinite(probe_xy[2 * p]) || !std::isfinite(probe_xy[2 * p + 1]))
+            return fail(PRISM_E_INVAL, "probe %lld: non-finite position", (long long)p);
+        xy[p] = make_double2(probe_xy[2 * p], probe_xy[2 * p + 1]);
+    }
+    Carve c(ws);
+    PropDev pd;
+    int *d_kymax, *d_perm, *d_bstart;
+    double2* d_xy;
+    float2 *T, *W;
+    float* I;
+    multislice_carve(c, n, nsl, n_probes, batch, n_bins, perm.size(), pd, d_kymax, d_perm, d_bstart, d_xy, T, W, I);
+    PropHost ph = prop_tables(n, L, lam, grid->dz);
+    std::vector<char> blob;
+    stage(blob, ws, pd.tw_half, ph.tw_half);
+    stage(blob, ws, pd.tw_full, ph.tw_full);
+    stage(blob, ws, pd.band, ph.band);
+    stage(blob, ws, pd.prop, ph.prop);
+    stage(blob, ws, d_kymax, kymax);
+    stage(blob, ws, d_perm, perm);
+    stage(blob, ws, d_bstart, bstart);
+    stage(blob, ws, d_xy, xy);
+    hipStream_t st = as_stream(stream);
+    rc = upload(ws, blob, st);
+    if (rc) return rc;
+    const PropTables tb = pd.tables();
+    HIP_TRY(launch_transmission(V, T, (int64_t)nsl * n * n, (float)sig, st));
+    const float amp = (float)(1.0 / std::sqrt((double)n_ap));
+    for (int64_t p0 = 0; p0 < n_probes; p0 += batch) {
+        const int nb = (int)std::min<int64_t>(batch, n_probes - p0);
+        HIP_TRY(launch_pass_b(n, PASSB_INIT, W, tb, nullptr, nullptr, d_kymax, d_xy + p0, 1.0 / L, amp, nb, st));
+        for (int s = 0; s < nsl; ++s) {
+            HIP_TRY(launch_pass_a(n, W, T + (size_t)s * n * n, tb, nullptr, false, nb, st));
+            HIP_TRY(launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_I : PASSB_MID, W, tb, nullptr, I, nullptr, nullptr,
+                                  0.0, 0.f, nb, st));
+        }
+        HIP_TRY(launch_bin_reduce(I, (int64_t)Lh * Lh, out + p0 * n_bins, d_perm, d_bstart, nb, n_bins, st));
+    }
+    return PRISM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+// fft.hpp -- wave-level complex FFTs for gfx950 (CDNA4, wave64).
+//
+// The multislice/PRISM propagation (Eq. 2) is a convolution done through
+// FFTs ("PRISM Probe Simulations": batched FFTs over many plane waves).  Here
+// every 1D transform of length L is owned by LPT = L/E lanes of one wavefront,
+// each lane holding E elements in registers in "natural" order:
+//     reg[i] of lane t  <->  element t + LPT * i.
+// A transform is a sequence of radix-R Stockham (autosort, decimation in
+// time) stages computed in registers; consecutive stages exchange data
+// through an LDS buffer private to the wavefront, so no workgroup barrier is
+// needed.  Input and output are both in natural order, which lets callers
+// load and store straight from/to coalesced global memory.
+//
+// Transforms are unnormalised in both directions (DIR = -1 forward
+// e^{-2 pi i jk/L}, DIR = +1 inverse e^{+2 pi i jk/L}).  Stage twiddles are
+// read once per kernel from an FP64-derived table W_L[m] = e^{-2 pi i m/L}
+// and kept in registers for every transform the wave performs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace prism {
+
+// ---------------------------------------------------------------- complex --
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// a * w for DIR = -1, a * conj(w) for DIR = +1 (w is a forward twiddle)
+template <int DIR>
+__device__ __forceinline__ float2 ctw(float2 a, float2 w) { return DIR < 0 ? cmul(a, w) : cmulc(a, w); }
+__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+
+// Ordering barrier for LDS traffic among the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------- register DFTs --
+// e^{DIR 2 pi i k / R} for compile-time k, R in {2, 4, 8, 16}; multiplication
+// specialised for the trivial and the 45-degree angles.
+template <int R, int K, int DIR>
+__device__ __forceinline__ float2 mul_root(float2 a) {
+    constexpr int k = ((K % R) + R) % R;
+    if constexpr (k == 0) {
+        return a;
+    } else if constexpr (4 * k == R) {            // DIR * i
+        return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+    } else if constexpr (2 * k == R) {            // -1
+        return make_float2(-a.x, -a.y);
+    } else if constexpr (4 * k == 3 * R) {        // -DIR * i
+        return DIR < 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+    } else {
+        // general angle: cos/sin of 2 pi k / R for R = 8, 16
+        constexpr double c16[16] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+                                    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+                                    -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
+                                    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
+        constexpr int m = k * (16 / R);
+        constexpr float c = (float)c16[m];
+        constexpr float s = (float)c16[(m + 12) % 16];   // sin(x) = cos(x - pi/2)
+        constexpr float sd = DIR < 0 ? -s : s;
+        if constexpr (m == 2 || m == 6 || m == 10 || m == 14) {
+            // (+-1 +- i) / sqrt(2)
+            return make_float2(c * a.x - sd * a.y, c * a.y + sd * a.x);
+        } else {
+            return make_float2(c * a.x - sd * a.y, sd * a.x + c * a.y);
+        }
+    }
+}
+
+template <int R, int DIR>
+struct Dft;
+
+template <int DIR>
+struct Dft<1, DIR> {
+    __device__ __forceinline__ static void run(float2*) {}
+};
+
+template <int DIR>
+struct Dft<2, DIR> {
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 a = v[0];
+        v[0] = cadd(a, v[1]);
+        v[1] = csub(a, v[1]);
+    }
+};
+
+// Radix-2 split of a length-R DFT into even/odd halves (natural order in/out).
+template <int R, int DIR>
+struct Dft {
+    template <int K>
+    __device__ __forceinline__ static void combine(float2* v, const float2* e, const float2* o) {
+        if constexpr (K < R / 2) {
+            float2 t = mul_root<R, K, DIR>(o[K]);
+            v[K] = cadd(e[K], t);
+            v[K + R / 2] = csub(e[K], t);
+            combine<K + 1>(v, e, o);
+        }
+    }
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        Dft<R / 2, DIR>::run(e);
+        Dft<R / 2, DIR>::run(o);
+        combine<0>(v, e, o);
+    }
+};
+
+// ------------------------------------------------------------ radix plans --
+// E: elements per lane; radices applied first to last (Ns = product of the
+// previous radices).  Every radix divides E.
+template <int L> struct Plan;
+template <> struct Plan<16>   { static constexpr int E = 4,  NST = 2; static constexpr int R[3] = {4, 4, 1}; };
+template <> struct Plan<32>   { static constexpr int E = 8,  NST = 2; static constexpr int R[3] = {8, 4, 1}; };
+template <> struct Plan<64>   { static constexpr int E = 8,  NST = 2; static constexpr int R[3] = {8, 8, 1}; };
+template <> struct Plan<128>  { static constexpr int E = 8,  NST = 3; static constexpr int R[3] = {8, 4, 4}; };
+template <> struct Plan<256>  { static constexpr int E = 8,  NST = 3; static constexpr int R[3] = {8, 8, 4}; };
+template <> struct Plan<512>  { static constexpr int E = 8,  NST = 3; static constexpr int R[3] = {8, 8, 8}; };
+template <> struct Plan<1024> { static constexpr int E = 16, NST = 3; static constexpr int R[3] = {16, 8, 8}; };
+
+template <int L>
+struct Fft {
+    static constexpr int E = Plan<L>::E;
+    static constexpr int NST = Plan<L>::NST;
+    static constexpr int LPT = L / E;                 // lanes per transform (<= 64)
+    static_assert(LPT <= 64, "one transform must fit in a wavefront");
+    static constexpr int LDS = L + L / 8;             // padded exchange buffer (float2)
+
+    static constexpr int radix(int s) { return Plan<L>::R[s]; }
+    static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
+    // twiddle registers per lane: for stages s >= 1, (E/R) work items x (R-1)
+    static constexpr int tw_off(int s) { return s <= 1 ? 0 : tw_off(s - 1) + (E / radix(s - 1)) * (radix(s - 1) - 1); }
+    static constexpr int NTW = tw_off(NST) > 0 ? tw_off(NST) : 1;
+
+    __device__ __forceinline__ static int pad(int i) { return i + (i >> 3); }
+
+    // Forward twiddles of this lane, read from W_L[m] = e^{-2 pi i m / L}.
+    struct Twiddles {
+        float2 w[NTW];
+        __device__ __forceinline__ void load(const float2* __restrict__ table, int lt) {
+            load_stage<1>(table, lt);
+        }
+        template <int S>
+        __device__ __forceinline__ void load_stage(const float2* __restrict__ table, int lt) {
+            if constexpr (S < NST) {
+                constexpr int R = radix(S), NS = ns(S), U = E / R;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    int j = lt + LPT * u;
+                    int k = j % NS;
+#pragma unroll
+                    for (int r = 1; r < R; ++r)
+                        w[tw_off(S) + u * (R - 1) + (r - 1)] = table[(r * k * (L / (NS * R))) % L];
+                }
+                load_stage<S + 1>(table, lt);
+            }
+        }
+    };
+
+    // LDS accessors of a transform's exchange space: a padded contiguous
+    // buffer (rows), or a strided column of a 2D LDS array.
+    struct RowX {
+        float2* p;
+        __device__ __forceinline__ float2& operator()(int i) const { return p[pad(i)]; }
+    };
+    struct ColX {
+        float2* p;
+        int stride;
+        __device__ __forceinline__ float2& operator()(int i) const { return p[i * stride]; }
+    };
+
+    template <int DIR, int S, class X>
+    __device__ __forceinline__ static void stage(float2 (&v)[E], const X& lds, const Twiddles& tw, int lt) {
+        constexpr int R = radix(S), NS = ns(S), U = E / R;
+        float2 out[E];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float2 w[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) w[r] = v[u + r * U];
+            if constexpr (S > 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[r] = ctw<DIR>(w[r], tw.w[tw_off(S) + u * (R - 1) + (r - 1)]);
+            }
+            Dft<R, DIR>::run(w);
+#pragma unroll
+            for (int r = 0; r < R; ++r) out[u * R + r] = w[r];
+        }
+        if constexpr (S == NST - 1) {
+            // last stage: outputs j + r*NS land in natural order
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[u + r * U] = out[u * R + r];
+        } else {
+            wave_sync();
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int j = lt + LPT * u;
+                int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds(base + r * NS) = out[u * R + r];
+            }
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = lds(lt + LPT * i);
+            stage<DIR, S + 1>(v, lds, tw, lt);
+        }
+    }
+
+    // In-place transform of the natural-order data v of lane lt (0..LPT-1);
+    // lds: this transform's private exchange buffer (LDS entries padded).
+    template <int DIR>
+    __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const Twiddles& tw, int lt) {
+        stage<DIR, 0>(v, RowX{lds}, tw, lt);
+    }
+    // Same, exchanging through the LDS column p[i * stride], i < L.
+    template <int DIR>
+    __device__ __forceinline__ static void run_col(float2 (&v)[E], float2* p, int stride, const Twiddles& tw, int lt) {
+        stage<DIR, 0>(v, ColX{p, stride}, tw, lt);
+    }
+};
+
+}  // namespace prism

@@ -1,0 +1,65 @@
+// kernels.hpp -- host-side launchers of the gfx950 kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace prism {
+
+// Band-limited wave buffer layout used by the propagation passes:
+//   W[item][j][y], j in [0, n/2) a band column (kx = j for j < n/4, j - n/2
+//   otherwise), y in [0, n) the real-space row.  One "item" is a beam
+//   (S-matrix) or a probe (multislice).
+struct PropTables {
+    const float2* tw_half;   // W_{n/2}[m] = e^{-2 pi i m/(n/2)}, n/2 entries
+    const float2* tw_full;   // W_n[m]     = e^{-2 pi i m/n},     n entries
+    const float2* band_tw;   // e^{-2 pi i kx(j)/n}, n/2 entries
+    const float2* prop;      // (1/n) e^{-i pi lambda dz kx(j)^2 / L^2}, n/2 entries
+};
+
+enum PassBMode { PASSB_MID = 0, PASSB_LAST_S = 1, PASSB_LAST_I = 2, PASSB_INIT = 3 };
+
+// T[s][y][x] = exp(i sigma V[s][y][x]) for count = n_slices*n*n pixels.
+hipError_t launch_transmission(const float* V, float2* T, int64_t count, float sigma, hipStream_t st);
+
+// Row pass: for each item and real-space row y, (optionally) inverse row
+// transform of the band, multiply by T[y][x], forward row transform, keep the
+// band.  first_pw: the input is the plane wave of the item's beam instead of W.
+hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb, const int2* beams,
+                         bool first_pw, int n_items, hipStream_t st);
+
+// Column pass (see PassBMode).  inten: band intensities [item][j][j'] for
+// PASSB_LAST_I; out_half: [item][j][my] for PASSB_LAST_S.  For PASSB_INIT the
+// spectrum is the aperture: |ky| <= ky_max[j], coefficient amp e^{-2 pi i (kx x + ky y)/L}.
+hipError_t launch_pass_b(int n, int mode, float2* W, const PropTables& tb, float2* out_half, float* inten,
+                         const int* ky_max, const double2* probe_xy, double inv_L, float amp, int n_items,
+                         hipStream_t st);
+
+// Final S-matrix pass: S[b][my][mx] = inverse row transform of half[b][j][my].
+hipError_t launch_smatrix_final(int n, const float2* half, float2* S, const float2* tw_half, int n_items,
+                                hipStream_t st);
+
+// ---- projected potential --------------------------------------------------
+struct PotAtom { double x, y; int32_t slice, species; };
+struct PotSpecies { float amp_n[4]; float inv2w2[4]; float rc2; int n_gauss; float rc; int pad; };
+hipError_t launch_potential(float* V, int n, int n_slices, double L, const PotAtom* atoms,
+                            const int* slice_start, const PotSpecies* species, float rc_max, hipStream_t st);
+
+// ---- probe synthesis ----------------------------------------------------------
+// C[p][b] = amp * exp(-2 pi i (kx_b x_p + ky_b y_p) / L) (FP64 argument, range reduced).
+hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, int n_probes, int n_beams,
+                               double inv_L, float amp, hipStream_t st);
+
+// Windowed contraction: win[p][v][u] = sum_b C[p][b] S[b][pix].
+hipError_t launch_contract(int precision, const float2* C, const float2* S, float2* win,
+                           const int* tile_start, const int* tile_probes, const int2* corner,
+                           int n_tiles, int max_per_tile, int n_beams, int ns, int m, hipStream_t st);
+
+// out[p][bin] = sum over the bin's pixels of |FFT_m(win[p])|^2 / m^4.
+hipError_t launch_window_detect(int m, const float2* win, float* out, const int* perm, const int* bin_start,
+                                const float2* tw_m, int n_probes, int n_bins, hipStream_t st);
+
+// out[p][bin] = sum over bin pixels of inten[p][pix] (deterministic order).
+hipError_t launch_bin_reduce(const float* inten, int64_t pix_per_item, float* out, const int* perm,
+                             const int* bin_start, int n_items, int n_bins, hipStream_t st);
+
+}  // namespace prism

@@ -1,0 +1,232 @@
+// probe.hip -- PRISM probe synthesis: coefficients, windowed beam contraction,
+// window FFT with |Psi|^2, and deterministic annular-detector sums.
+//
+// "PRISM Probe Simulations": each probe is a sum over plane waves of the
+// cropped S-matrix layers times per-beam phase coefficients; the modulus
+// squared of the FFT of that exit wave is binned into detectors (Fig. 1i-k).
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace prism {
+
+constexpr int WG = 256;
+
+// ------------------------------------------------------------ coefficients --
+// C[p][b] = amp e^{-2 pi i (kx x + ky y)/L}; the phase argument is formed in
+// FP64 and reduced to [-1/2, 1/2] turns before the FP32 sincos.
+__global__ __launch_bounds__(WG) void k_coefficients(float2* __restrict__ C, const double2* __restrict__ xy,
+                                                     const int2* __restrict__ beams, int n_probes, int n_beams,
+                                                     double inv_L, float amp) {
+    int64_t total = (int64_t)n_probes * n_beams;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
+        int p = (int)(i / n_beams), b = (int)(i % n_beams);
+        double2 r = xy[p];
+        int2 k = beams[b];
+        double a = ((double)k.x * r.x + (double)k.y * r.y) * inv_L;
+        float fr = (float)(a - rint(a));
+        float s, c;
+        sincosf(-6.283185307179586f * fr, &s, &c);
+        C[i] = make_float2(amp * c, amp * s);
+    }
+}
+
+hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, int n_probes, int n_beams,
+                               double inv_L, float amp, hipStream_t st) {
+    int64_t total = (int64_t)n_probes * n_beams;
+    int64_t blocks = (total + WG - 1) / WG;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_coefficients, dim3((unsigned)blocks), dim3(WG), 0, st, C, xy, beams, n_probes, n_beams,
+                       inv_L, amp);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------- windowed contraction --
+// The S grid is cut into 16 x 16 pixel tiles.  For each tile the plan lists
+// every probe whose M x M window overlaps it.  A workgroup takes one tile and
+// a chunk of PC of those probes and forms, for every tile pixel,
+//     acc[p] = sum_b C[p][b] S[b][pixel]
+// then stores each (probe, pixel) that lies inside the probe's window.  Each
+// window element is produced by exactly one (tile, probe) pair, so no atomics.
+constexpr int TILE = 16;
+
+namespace fp32c {
+constexpr int PC = 32;   // probes per workgroup
+constexpr int KB = 32;   // beams per LDS chunk
+}
+
+__global__ __launch_bounds__(WG) void k_contract_fp32(const float2* __restrict__ C, const float2* __restrict__ S,
+                                                      float2* __restrict__ win, const int* __restrict__ tile_start,
+                                                      const int* __restrict__ tile_probes,
+                                                      const int2* __restrict__ corner, int n_beams, int ns, int m) {
+    using namespace fp32c;
+    __shared__ float2 cs[KB][PC];
+    __shared__ int pidx[PC];
+    const int tile = blockIdx.x;
+    const int t0 = tile_start[tile], t1 = tile_start[tile + 1];
+    const int pc0 = t0 + (int)blockIdx.y * PC;
+    if (pc0 >= t1) return;
+    const int np = min(PC, t1 - pc0);
+    const int ntx = ns / TILE;
+    const int tid = threadIdx.x;
+    const int px = (tile % ntx) * TILE + (tid % TILE);
+    const int py = (tile / ntx) * TILE + (tid / TILE);
+    if (tid < PC) pidx[tid] = tid < np ? tile_probes[pc0 + tid] : -1;
+    __syncthreads();
+
+    float2 acc[PC];
+#pragma unroll
+    for (int p = 0; p < PC; ++p) acc[p] = make_float2(0.f, 0.f);
+    const size_t plane = (size_t)ns * ns;
+    const float2* Sp = S + (size_t)py * ns + px;
+
+    for (int b0 = 0; b0 < n_beams; b0 += KB) {
+        for (int e = tid; e < KB * PC; e += WG) {
+            int p = e / KB, kk = e % KB;
+            float2 v = make_float2(0.f, 0.f);
+            if (p < np && b0 + kk < n_beams) v = C[(size_t)pidx[p] * n_beams + b0 + kk];
+            cs[kk][p] = v;
+        }
+        __syncthreads();
+        const int kb = min(KB, n_beams - b0);
+        float2 s[KB];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) s[kk] = kk < kb ? Sp[(size_t)(b0 + kk) * plane] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+#pragma unroll
+            for (int p = 0; p < PC; ++p) {
+                float2 c = cs[kk][p];
+                acc[p].x += c.x * s[kk].x - c.y * s[kk].y;
+                acc[p].y += c.x * s[kk].y + c.y * s[kk].x;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < PC; ++p) {
+        if (p < np) {
+            int q = pidx[p];
+            int2 c0 = corner[q];
+            int v = (py - c0.y) & (ns - 1);
+            int u = (px - c0.x) & (ns - 1);
+            if (v < m && u < m) win[(size_t)q * m * m + (size_t)v * m + u] = acc[p];
+        }
+    }
+}
+
+hipError_t launch_contract(int precision, const float2* C, const float2* S, float2* win, const int* tile_start,
+                           const int* tile_probes, const int2* corner, int n_tiles, int max_per_tile, int n_beams,
+                           int ns, int m, hipStream_t st) {
+    (void)precision;
+    using namespace fp32c;
+    dim3 grid((unsigned)n_tiles, (unsigned)((max_per_tile + PC - 1) / PC));
+    hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes, corner, n_beams,
+                       ns, m);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ deterministic bin sums --
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------- window detection --
+// One workgroup per probe: M x M window in LDS, row then column transforms,
+// |Psi|^2 / M^4, then each bin summed over its pixel list by one wavefront.
+template <int M>
+__global__ __launch_bounds__(WG) void k_window_detect(const float2* __restrict__ win, float* __restrict__ out,
+                                                      const int* __restrict__ perm,
+                                                      const int* __restrict__ bin_start,
+                                                      const float2* __restrict__ tw_m, int n_bins) {
+    using F = Fft<M>;
+    constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, ROW = F::LDS + 1;
+    __shared__ float2 buf[M * ROW];
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane / LPT, lt = lane % LPT;
+    const float2* w = win + (size_t)p * M * M;
+    for (int idx = tid; idx < M * M; idx += WG) buf[(idx / M) * ROW + F::pad(idx % M)] = w[idx];
+    __syncthreads();
+    typename F::Twiddles tw;
+    tw.load(tw_m, lt);
+    // rows
+    for (int r0 = wave * G; r0 < M; r0 += 4 * G) {
+        float2* row = buf + (r0 + g) * ROW;
+        float2 v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = row[F::pad(lt + LPT * i)];
+        F::template run<-1>(v, row, tw, lt);
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < E; ++i) row[F::pad(lt + LPT * i)] = v[i];
+    }
+    __syncthreads();
+    // columns, then intensity in place
+    const float scale = 1.0f / ((float)M * (float)M * (float)M * (float)M);
+    for (int c0 = wave * G; c0 < M; c0 += 4 * G) {
+        float2* col = buf + F::pad(c0 + g);
+        float2 v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = col[(lt + LPT * i) * ROW];
+        F::template run_col<-1>(v, col, ROW, tw, lt);
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < E; ++i) col[(lt + LPT * i) * ROW] = make_float2(cnorm(v[i]) * scale, 0.f);
+    }
+    __syncthreads();
+    for (int b = wave; b < n_bins; b += 4) {
+        float s = 0.f;
+        for (int k = bin_start[b] + lane; k < bin_start[b + 1]; k += 64) {
+            int pix = perm[k];
+            s += buf[(pix / M) * ROW + F::pad(pix % M)].x;
+        }
+        s = wave_sum(s);
+        if (lane == 0) out[(size_t)p * n_bins + b] = s;
+    }
+}
+
+template <int M>
+static hipError_t window_m(const float2* win, float* out, const int* perm, const int* bin_start, const float2* tw_m,
+                           int n_probes, int n_bins, hipStream_t st) {
+    hipLaunchKernelGGL((k_window_detect<M>), dim3((unsigned)n_probes), dim3(WG), 0, st, win, out, perm, bin_start, tw_m,
+                       n_bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_detect(int m, const float2* win, float* out, const int* perm, const int* bin_start,
+                                const float2* tw_m, int n_probes, int n_bins, hipStream_t st) {
+    switch (m) {
+        case 16: return window_m<16>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
+        case 32: return window_m<32>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
+        case 64: return window_m<64>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
+        case 128: return window_m<128>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------- bin reduce --
+__global__ __launch_bounds__(WG) void k_bin_reduce(const float* __restrict__ inten, int64_t pix_per_item,
+                                                   float* __restrict__ out, const int* __restrict__ perm,
+                                                   const int* __restrict__ bin_start, int n_bins) {
+    const int item = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const float* I = inten + (size_t)item * pix_per_item;
+    for (int b = wave; b < n_bins; b += 4) {
+        float s = 0.f;
+        for (int k = bin_start[b] + lane; k < bin_start[b + 1]; k += 64) s += I[perm[k]];
+        s = wave_sum(s);
+        if (lane == 0) out[(size_t)item * n_bins + b] = s;
+    }
+}
+
+hipError_t launch_bin_reduce(const float* inten, int64_t pix_per_item, float* out, const int* perm,
+                             const int* bin_start, int n_items, int n_bins, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_reduce, dim3((unsigned)n_items), dim3(WG), 0, st, inten, pix_per_item, out, perm,
+                       bin_start, n_bins);
+    return hipGetLastError();
+}
+
+}  // namespace prism

@@ -1,0 +1,357 @@
+// propagate.hip -- transmission and band-limited Fresnel propagation passes.
+//
+// One multislice step is transmission by exp(i sigma V_s) in real space
+// (Eq. 1) followed by the Fresnel propagator exp(-i pi lambda |q|^2 dz) in
+// Fourier space (Eq. 2), restricted to |q| < 1/(4 dx).  The band limit means a
+// wave never holds energy at |kx| >= n/4, so between passes only the n/2
+// band columns of the x-spectrum are stored:  W[item][j][y] (8 B each).
+//
+//   pass A (rows):    band row -> inverse row DFT -> x T_s -> forward row DFT -> band row
+//   pass B (columns): column    -> forward column DFT -> x P (mask, phase, 1/n^2)
+//                               -> inverse column DFT -> column
+//
+// An n-point transform whose input (inverse) or output (forward) is confined
+// to the band splits exactly into two n/2-point transforms over the even and
+// odd samples:
+//   psi(2m)   = IDFT_{n/2}[Phi_j](m)
+//   psi(2m+1) = IDFT_{n/2}[Phi_j e^{+2 pi i kx(j)/n}](m)
+//   Phi_j     = DFT_{n/2}[psi(2m)]_j + e^{-2 pi i kx(j)/n} DFT_{n/2}[psi(2m+1)]_j
+// so all transforms here have length n/2 and live in one wavefront.
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace prism {
+
+constexpr int WG = 256;      // 4 wavefronts
+
+template <int N>
+struct RowCfg {
+    static constexpr int L = N / 2;
+    using F = Fft<L>;
+    static constexpr int E = F::E;
+    static constexpr int LPT = F::LPT;
+    static constexpr int G = 64 / LPT;                       // transforms per wave at once
+    static constexpr int TR0 = (N <= 1024) ? 16 : 8;         // rows per workgroup (tile height)
+    static constexpr int TR = TR0 > 4 * G ? TR0 : 4 * G;
+    static constexpr int ROW = F::LDS + 1;                   // odd LDS row stride (float2)
+};
+
+// ------------------------------------------------------------ transmission --
+__global__ __launch_bounds__(WG) void k_transmission(const float* __restrict__ V, float2* __restrict__ T,
+                                                     int64_t count, float sigma) {
+    int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * WG;
+    for (; i < count; i += stride) {
+        float s, c;
+        sincosf(sigma * V[i], &s, &c);
+        T[i] = make_float2(c, s);
+    }
+}
+
+hipError_t launch_transmission(const float* V, float2* T, int64_t count, float sigma, hipStream_t st) {
+    int64_t blocks = (count + WG - 1) / WG;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_transmission, dim3((unsigned)blocks), dim3(WG), 0, st, V, T, count, sigma);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ pass A --
+template <int N, bool FIRST>
+__global__ __launch_bounds__(WG) void k_pass_a(float2* __restrict__ W, const float2* __restrict__ T, PropTables tb,
+                                               const int2* __restrict__ beams, int n_items) {
+    using C = RowCfg<N>;
+    using F = typename C::F;
+    constexpr int L = C::L, E = C::E, LPT = C::LPT, G = C::G, TR = C::TR, ROW = C::ROW;
+    __shared__ float2 tile[TR * ROW];
+
+    const int item = blockIdx.x % n_items;
+    const int y0 = (blockIdx.x / n_items) * TR;
+    float2* Wi = W + (size_t)item * L * N;
+    const int tid = threadIdx.x;
+
+    if constexpr (!FIRST) {
+        for (int idx = tid; idx < L * TR; idx += WG) {
+            int yy = idx % TR, j = idx / TR;
+            tile[yy * ROW + F::pad(j)] = Wi[(size_t)j * N + y0 + yy];
+        }
+        __syncthreads();
+    }
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int g = lane / LPT, lt = lane % LPT;
+    typename F::Twiddles tw;
+    tw.load(tb.tw_half, lt);
+    float2 btw[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) btw[i] = tb.band_tw[lt + LPT * i];
+    int kx = 0, ky = 0;
+    if constexpr (FIRST) {
+        int2 k = beams[item];
+        kx = k.x;
+        ky = k.y;
+    }
+
+    for (int r0 = wave * G; r0 < TR; r0 += 4 * G) {
+        const int yy = r0 + g, y = y0 + yy;
+        float2* row = tile + yy * ROW;
+        float2 e[E], o[E];
+        if constexpr (FIRST) {
+            // plane wave e^{2 pi i (kx x + ky y)/N} at x = 2m, 2m+1 (exact integer phase)
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                int m = lt + LPT * i;
+                int ph = (kx * 2 * m + ky * y) & (N - 1);
+                float2 w0 = tb.tw_full[ph];
+                float2 w1 = tb.tw_full[(ph + kx) & (N - 1)];
+                e[i] = make_float2(w0.x, -w0.y);
+                o[i] = make_float2(w1.x, -w1.y);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                e[i] = row[F::pad(lt + LPT * i)];
+                o[i] = cmulc(e[i], btw[i]);
+            }
+            F::template run<+1>(e, row, tw, lt);
+            F::template run<+1>(o, row, tw, lt);
+        }
+        const float4* Trow = reinterpret_cast<const float4*>(T + (size_t)y * N);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            float4 t = Trow[lt + LPT * i];
+            e[i] = cmul(e[i], make_float2(t.x, t.y));
+            o[i] = cmul(o[i], make_float2(t.z, t.w));
+        }
+        F::template run<-1>(e, row, tw, lt);
+        F::template run<-1>(o, row, tw, lt);
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < E; ++i) row[F::pad(lt + LPT * i)] = cadd(e[i], cmul(btw[i], o[i]));
+    }
+    __syncthreads();
+    for (int idx = tid; idx < L * TR; idx += WG) {
+        int yy = idx % TR, j = idx / TR;
+        Wi[(size_t)j * N + y0 + yy] = tile[yy * ROW + F::pad(j)];
+    }
+}
+
+template <int N>
+static hipError_t pass_a_n(float2* W, const float2* T, const PropTables& tb, const int2* beams, bool first,
+                           int n_items, hipStream_t st) {
+    constexpr int TR = RowCfg<N>::TR;
+    dim3 grid((unsigned)((size_t)n_items * (N / TR)));
+    if (first)
+        hipLaunchKernelGGL((k_pass_a<N, true>), grid, dim3(WG), 0, st, W, T, tb, beams, n_items);
+    else
+        hipLaunchKernelGGL((k_pass_a<N, false>), grid, dim3(WG), 0, st, W, T, tb, beams, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb, const int2* beams, bool first_pw,
+                         int n_items, hipStream_t st) {
+    switch (n) {
+        case 64: return pass_a_n<64>(W, T, tb, beams, first_pw, n_items, st);
+        case 128: return pass_a_n<128>(W, T, tb, beams, first_pw, n_items, st);
+        case 256: return pass_a_n<256>(W, T, tb, beams, first_pw, n_items, st);
+        case 512: return pass_a_n<512>(W, T, tb, beams, first_pw, n_items, st);
+        case 1024: return pass_a_n<1024>(W, T, tb, beams, first_pw, n_items, st);
+        case 2048: return pass_a_n<2048>(W, T, tb, beams, first_pw, n_items, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ pass B --
+template <int N, int MODE>
+__global__ __launch_bounds__(WG) void k_pass_b(float2* __restrict__ W, PropTables tb, float2* __restrict__ out_half,
+                                               float* __restrict__ inten, const int* __restrict__ ky_max,
+                                               const double2* __restrict__ probe_xy, double inv_L, float amp,
+                                               int n_items) {
+    using F = Fft<N / 2>;
+    constexpr int L = N / 2, E = F::E, LPT = F::LPT, G = 64 / LPT, CPB = 4 * G;
+    __shared__ float2 xch[CPB * F::LDS];
+
+    const int item = blockIdx.x % n_items;
+    const int cb = blockIdx.x / n_items;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane / LPT, lt = lane % LPT;
+    const int j = cb * CPB + wave * G + g;
+    if (j >= L) return;                          // whole transform groups exit together
+    float2* lds = xch + (wave * G + g) * F::LDS;
+    const int kxj = j < N / 4 ? j : j - N / 2;
+
+    typename F::Twiddles tw;
+    tw.load(tb.tw_half, lt);
+    float2 btw[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) btw[i] = tb.band_tw[lt + LPT * i];
+
+    float2* col = W + ((size_t)item * L + j) * N;
+    float4* col4 = reinterpret_cast<float4*>(col);
+    float2 e[E], o[E];
+
+    if constexpr (MODE == PASSB_INIT) {
+        // aperture spectrum of the probe at (x, y): amp e^{-2 pi i (kx x + ky y) / L}
+        const double2 p = probe_xy[item];
+        const int kym = ky_max[j];
+        const double ax = (double)kxj * p.x * inv_L;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            int jp = lt + LPT * i;
+            int ky = jp < N / 4 ? jp : jp - N / 2;
+            float2 c = make_float2(0.f, 0.f);
+            if (ky <= kym && -ky <= kym) {
+                double a = ax + (double)ky * p.y * inv_L;
+                float fr = (float)(a - rint(a));
+                float s, cs;
+                sincosf(-6.283185307179586f * fr, &s, &cs);
+                c = make_float2(amp * cs, amp * s);
+            }
+            e[i] = c;
+            o[i] = cmulc(c, btw[i]);
+        }
+        F::template run<+1>(e, lds, tw, lt);
+        F::template run<+1>(o, lds, tw, lt);
+#pragma unroll
+        for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
+        return;
+    }
+
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        float4 v = col4[lt + LPT * i];
+        e[i] = make_float2(v.x, v.y);
+        o[i] = make_float2(v.z, v.w);
+    }
+    F::template run<-1>(e, lds, tw, lt);
+    F::template run<-1>(o, lds, tw, lt);
+    const float2 pj = tb.prop[j];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        int jp = lt + LPT * i;
+        int ky = jp < N / 4 ? jp : jp - N / 2;
+        float2 psi = cadd(e[i], cmul(btw[i], o[i]));
+        bool in = 16 * (kxj * kxj + ky * ky) < N * N;
+        e[i] = in ? cmul(psi, cmul(pj, tb.prop[jp])) : make_float2(0.f, 0.f);
+    }
+    if constexpr (MODE == PASSB_LAST_I) {
+        float* dst = inten + ((size_t)item * L + j) * L;
+#pragma unroll
+        for (int i = 0; i < E; ++i) dst[lt + LPT * i] = cnorm(e[i]);
+        return;
+    }
+    if constexpr (MODE == PASSB_LAST_S) {
+        // even rows only: psi(2 my) for my in [0, n/2), written over the
+        // first half of this (already loaded) column
+        F::template run<+1>(e, lds, tw, lt);
+#pragma unroll
+        for (int i = 0; i < E; ++i) col[lt + LPT * i] = e[i];
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) o[i] = cmulc(e[i], btw[i]);
+    F::template run<+1>(e, lds, tw, lt);
+    F::template run<+1>(o, lds, tw, lt);
+#pragma unroll
+    for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
+}
+
+template <int N, int MODE>
+static hipError_t pass_b_nm(float2* W, const PropTables& tb, float2* out_half, float* inten, const int* ky_max,
+                            const double2* xy, double inv_L, float amp, int n_items, hipStream_t st) {
+    constexpr int L = N / 2, LPT = Fft<L>::LPT, CPB = 4 * (64 / LPT);
+    dim3 grid((unsigned)((size_t)n_items * ((L + CPB - 1) / CPB)));
+    hipLaunchKernelGGL((k_pass_b<N, MODE>), grid, dim3(WG), 0, st, W, tb, out_half, inten, ky_max, xy, inv_L, amp,
+                       n_items);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t pass_b_n(int mode, float2* W, const PropTables& tb, float2* out_half, float* inten,
+                           const int* ky_max, const double2* xy, double inv_L, float amp, int n_items,
+                           hipStream_t st) {
+    switch (mode) {
+        case PASSB_MID: return pass_b_nm<N, PASSB_MID>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
+        case PASSB_LAST_S:
+            return pass_b_nm<N, PASSB_LAST_S>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
+        case PASSB_LAST_I:
+            return pass_b_nm<N, PASSB_LAST_I>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
+        case PASSB_INIT: return pass_b_nm<N, PASSB_INIT>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass_b(int n, int mode, float2* W, const PropTables& tb, float2* out_half, float* inten,
+                         const int* ky_max, const double2* probe_xy, double inv_L, float amp, int n_items,
+                         hipStream_t st) {
+    switch (n) {
+        case 64: return pass_b_n<64>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 128: return pass_b_n<128>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 256: return pass_b_n<256>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 512: return pass_b_n<512>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 1024: return pass_b_n<1024>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 2048: return pass_b_n<2048>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------- S-matrix final pass --
+// W[b][j][my], my < n/2 (band x-spectrum of the even rows, left in the wave
+// buffer by the last column pass) -> S[b][my][mx] = psi(2my, 2mx).
+template <int N>
+__global__ __launch_bounds__(WG) void k_smatrix_final(const float2* __restrict__ half, float2* __restrict__ S,
+                                                      const float2* __restrict__ tw_half, int n_items) {
+    using C = RowCfg<N>;
+    using F = typename C::F;
+    constexpr int L = C::L, E = C::E, LPT = C::LPT, G = C::G, TR = C::TR, ROW = C::ROW;
+    constexpr int TRV = TR < L ? TR : L;         // valid rows per block
+    __shared__ float2 tile[TR * ROW];
+
+    const int item = blockIdx.x % n_items;
+    const int y0 = (blockIdx.x / n_items) * TRV;
+    const float2* Hi = half + (size_t)item * L * N;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < L * TRV; idx += WG) {
+        int yy = idx % TRV, j = idx / TRV;
+        tile[yy * ROW + F::pad(j)] = Hi[(size_t)j * N + y0 + yy];
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    const int g = lane / LPT, lt = lane % LPT;
+    typename F::Twiddles tw;
+    tw.load(tw_half, lt);
+    for (int r0 = wave * G; r0 < TRV; r0 += 4 * G) {
+        const int yy = r0 + g;
+        if (yy >= TRV) break;
+        float2* row = tile + yy * ROW;
+        float2 v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = row[F::pad(lt + LPT * i)];
+        F::template run<+1>(v, row, tw, lt);
+        float2* dst = S + ((size_t)item * L + y0 + yy) * L;
+#pragma unroll
+        for (int i = 0; i < E; ++i) dst[lt + LPT * i] = v[i];
+    }
+}
+
+template <int N>
+static hipError_t final_n(const float2* half, float2* S, const float2* tw_half, int n_items, hipStream_t st) {
+    constexpr int L = N / 2, TR = RowCfg<N>::TR, TRV = TR < L ? TR : L;
+    dim3 grid((unsigned)((size_t)n_items * (L / TRV)));
+    hipLaunchKernelGGL((k_smatrix_final<N>), grid, dim3(WG), 0, st, half, S, tw_half, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_smatrix_final(int n, const float2* half, float2* S, const float2* tw_half, int n_items,
+                                hipStream_t st) {
+    switch (n) {
+        case 64: return final_n<64>(half, S, tw_half, n_items, st);
+        case 128: return final_n<128>(half, S, tw_half, n_items, st);
+        case 256: return final_n<256>(half, S, tw_half, n_items, st);
+        case 512: return final_n<512>(half, S, tw_half, n_items, st);
+        case 1024: return final_n<1024>(half, S, tw_half, n_items, st);
+        case 2048: return final_n<2048>(half, S, tw_half, n_items, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace prism

@@ -1,0 +1,120 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates its arguments, and its host-side integer planning
+(beam sets, detector bin maps) equals the oracle's bit for bit."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1706_08563_amd as P
+    return P
+
+
+def test_library_exports_every_declared_symbol():
+    P = _lib()
+    hdr = open(os.path.join(ROOT, "include", "prism.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"^\s*(?:int|const char\s*\*)\s+(\w+)\s*\(", hdr, flags=re.M))
+    assert declared, "no declarations parsed"
+    raw = ctypes.CDLL(P.LIB_PATH)
+    for name in declared:
+        assert hasattr(raw, name), name
+    assert declared == set(P.EXPORTED)
+
+
+def test_grid_validation_codes():
+    P = _lib()
+    g = P.prism_grid_init((20.0, 20.0, 20.0), 2.0, 256)
+    assert g.n_slices == 10
+    with pytest.raises(P.PrismError) as e:
+        P.prism_grid_init((20.0, 20.0, 20.0), 2.0, 250)
+    assert e.value.code == P.PRISM_E_UNSUPPORTED
+    with pytest.raises(P.PrismError) as e:
+        P.prism_grid_init((20.0, 21.0, 20.0), 2.0, 256)
+    assert e.value.code == P.PRISM_E_UNSUPPORTED
+    with pytest.raises(P.PrismError) as e:
+        P.prism_grid_init((20.0, 20.0, 20.0), 0.0, 256)
+    assert e.value.code == P.PRISM_E_INVAL
+    g = P.prism_grid_init((20.0, 20.0, 7.0), 2.0, 64)
+    assert g.n_slices == 4
+
+
+def test_smatrix_plan_validation_codes():
+    P = _lib()
+    g = P.prism_grid_init((20.0, 20.0, 20.0), 2.0, 256)
+    for args, code in [((80e3, 0.2, 2), P.PRISM_E_UNSUPPORTED),   # alpha_max above alpha_AA
+                       ((80e3, 0.02, 3), P.PRISM_E_UNSUPPORTED),   # f does not divide n/2
+                       ((80e3, 0.02, 16), P.PRISM_E_UNSUPPORTED),  # window 8 < 16
+                       ((-1.0, 0.02, 2), P.PRISM_E_INVAL),
+                       ((80e3, 0.02, 0), P.PRISM_E_INVAL)]:
+        with pytest.raises(P.PrismError) as e:
+            P.prism_smatrix_plan(g, *args)
+        assert e.value.code == code, args
+
+
+@pytest.mark.parametrize("cfg", [0, 2, 3])
+def test_plan_constants_and_beams_match_oracle(cfg):
+    P = _lib()
+    w = W.CONFIGS[cfg]
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    lam = O.wavelength(w.E0)
+    assert abs(d.lambda_ - lam) <= 1e-15 * lam
+    assert abs(d.sigma - O.interaction_constant(w.E0)) <= 1e-15 * d.sigma
+    assert d.alpha_aa == O.alpha_aa(lam, w.n, w.cell[0])
+    ob = O.beam_set(w.n, w.cell[0], lam, w.alpha_max, w.f)
+    gb = P.prism_beam_list(d)
+    assert gb.shape == ob.shape and np.array_equal(gb, ob)
+    assert d.m_win == w.n // 2 // w.f
+
+
+@pytest.mark.parametrize("m,f,cfg", [(64, 2, 0), (128, 4, 2), (128, 8, 3), (256, 1, 0), (1024, 1, 1)])
+def test_bin_map_bit_exact(m, f, cfg):
+    P = _lib()
+    w = W.CONFIGS[cfg]
+    L = w.cell[0]
+    lam = O.wavelength(w.E0)
+    a_aa = O.alpha_aa(lam, w.n, L)
+    nb = O.default_n_bins(lam, w.n, L, 1e-3)
+    Lw = L / f
+    ref = O.bin_map(lam, m, Lw, a_aa, 1e-3, nb)
+    got = P.prism_detector_bin_map(lam, Lw, a_aa, 1e-3, nb, m)
+    assert np.array_equal(ref, got)
+
+
+def test_bin_map_edges_and_explicit_bin_count():
+    P = _lib()
+    lam, Lw = 0.025, 25.0
+    for m, nb in [(64, 16), (64, 5), (32, 3)]:
+        a_aa = O.alpha_aa(lam, 2 * m, 2 * Lw)
+        assert np.array_equal(P.prism_detector_bin_map(lam, Lw, a_aa, 1e-3, nb, m),
+                              O.bin_map(lam, m, Lw, a_aa, 1e-3, nb))
+
+
+def test_probe_plan_sizes():
+    P = _lib()
+    w = W.CONFIGS[0]
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    xy = W.scan_positions(w.cell, *w.scan)
+    p = P.prism_probe_plan_init(d, xy)
+    assert p.n_probes == 256 and p.n_bins == 134
+    # each probe window (64 px) overlaps 4 or 5 tiles of 16 px per axis
+    assert 256 * 16 <= p.n_entries <= 256 * 25
+    # the binned pixel count equals the oracle bin map's
+    lam = O.wavelength(w.E0)
+    bm = O.bin_map(lam, 64, w.cell[0] / 2, O.alpha_aa(lam, w.n, w.cell[0]), 1e-3, 134)
+    assert p.n_binned == int((bm >= 0).sum())
+    with pytest.raises(P.PrismError) as e:
+        P.prism_probe_plan_init(d, np.array([[np.nan, 0.0]]))
+    assert e.value.code == P.PRISM_E_INVAL

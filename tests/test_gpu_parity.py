@@ -1,0 +1,209 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Inputs are seeded (workloads module); the oracle computes the expected values
+on the CPU.  Tolerances: FP32 arithmetic on the GPU is gated at 1e-4 relative
+(Frobenius norm over probes x bins, and over the dark-field signal); element
+arrays (potential, S-matrix) at 1e-4 of their largest magnitude.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_1706_08563_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _gpu_potential(P, w, pos, sp):
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    V = P.prism_project_potential(pos, sp, w.species, g)
+    _sync()
+    return g, V
+
+
+def _random_potential(rng, S, n, vmax=60.0):
+    return rng.uniform(0.0, vmax, size=(S, n, n))
+
+
+# ---------------------------------------------------------------- potential --
+@pytest.mark.parametrize("n,cell,n_atoms,seed", [(64, (10.0, 10.0, 6.0), 12, 0), (128, (16.0, 16.0, 4.0), 40, 1)])
+def test_potential_parity_small(P, n, cell, n_atoms, seed):
+    say(f"potential n={n} atoms={n_atoms} seed={seed}")
+    w, pos, sp = W.small_workload(n=n, cell=cell, n_atoms=n_atoms, seed=seed)
+    g, V = _gpu_potential(P, w, pos, sp)
+    ref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    got = V.cpu().numpy().astype(np.float64)
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_potential_parity_config0(P):
+    say("potential config0 256^2")
+    w = W.CONFIGS[0]
+    pos, sp = W.atoms_for(w)
+    g, V = _gpu_potential(P, w, pos, sp)
+    ref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    got = V.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+# ----------------------------------------------------------------- S-matrix --
+@pytest.mark.parametrize("n,L,S,f,E0", [(64, 10.0, 3, 2, 80e3), (128, 16.0, 2, 1, 200e3), (256, 20.0, 2, 4, 80e3),
+                                        (512, 40.0, 2, 4, 200e3)])
+def test_smatrix_parity_random_potential(P, n, L, S, f, E0):
+    import torch
+    say(f"smatrix n={n} S={S} f={f}")
+    rng = np.random.default_rng(n + S)
+    Vr = _random_potential(rng, S, n)
+    g = P.prism_grid_init((L, L, 2.0 * S), 2.0, n)
+    d = P.prism_smatrix_plan(g, E0, 0.02, f)
+    V = torch.tensor(Vr, dtype=torch.float32, device="cuda")
+    Sg = P.prism_build_smatrix(d, V)
+    _sync()
+    beams = O.beam_set(n, L, d.lambda_, 0.02, f)
+    # the oracle sees the potential the GPU was given (rounded to float32)
+    ref = O.build_smatrix(Vr.astype(np.float32).astype(np.float64), L, 2.0, d.lambda_, d.sigma, beams)
+    got = Sg.cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say(f"  max rel err {err:.3e}")
+    assert err <= TOL
+
+
+# ------------------------------------------------------------ probe outputs --
+def _check_D(got, ref, label):
+    e_all = O.rel_err(got, ref)
+    e_adf = O.rel_err(O.adf_signal(got, 1e-3, 0.04), O.adf_signal(ref, 1e-3, 0.04))
+    say(f"  {label}: rel_all={e_all:.3e} rel_adf={e_adf:.3e}")
+    assert e_all <= TOL and e_adf <= TOL
+
+
+@pytest.mark.parametrize("n,f,scan,seed", [(64, 2, (4, 4), 0), (128, 2, (5, 3), 1), (256, 4, (3, 7), 2)])
+def test_prism_end_to_end_small(P, n, f, scan, seed):
+    say(f"prism e2e n={n} f={f} scan={scan}")
+    cell = (10.0 * n / 64, 10.0 * n / 64, 6.0)
+    w, pos, sp = W.small_workload(n=n, cell=cell, n_atoms=int(12 * (n / 64) ** 2), f=f, scan=scan, seed=seed)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, f)
+    Sg = P.prism_build_smatrix(d, V)
+    xy = W.scan_positions(w.cell, *scan)
+    plan = P.prism_probe_plan_upload(d, xy)
+    out = P.prism_probe_outputs(d, Sg, plan, P.PRISM_FP32)
+    _sync()
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    beams = O.beam_set(n, w.cell[0], d.lambda_, w.alpha_max, f)
+    Sref = O.build_smatrix(Vref, w.cell[0], w.dz, d.lambda_, d.sigma, beams)
+    ref = O.prism_outputs(Sref, beams, w.cell[0], n, d.lambda_, f, xy)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "fp32")
+
+
+def test_prism_synthesis_random_smatrix(P):
+    """Probe synthesis alone on a seeded random S-matrix, random probe positions."""
+    import torch
+    say("prism synthesis random S n=256 f=2 random probes")
+    n, L, f = 256, 20.0, 2
+    g = P.prism_grid_init((L, L, 2.0), 2.0, n)
+    d = P.prism_smatrix_plan(g, 80e3, 0.02, f)
+    rng = np.random.default_rng(11)
+    S = W.random_complex((d.n_beams, d.ns, d.ns), rng)
+    xy = np.concatenate([W.random_positions((L, L), 37, rng), [[0.0, 0.0], [L - 1e-9, L - 1e-9], [-3.0, 25.0]]])
+    plan = P.prism_probe_plan_upload(d, xy)
+    out = P.prism_probe_outputs(d, torch.tensor(S, device="cuda"), plan, P.PRISM_FP32)
+    _sync()
+    beams = O.beam_set(n, L, d.lambda_, 0.02, f)
+    ref = O.prism_outputs(S.astype(np.complex128), beams, L, n, d.lambda_, f, xy)
+    got = out.cpu().numpy().astype(np.float64)
+    assert O.rel_err(got, ref) <= TOL
+    assert np.max(np.abs(got - ref) / (np.abs(ref) + 1e-3 * np.abs(ref).max())) <= 10 * TOL
+
+
+# ------------------------------------------------------------------ vacuum --
+@pytest.mark.parametrize("f", [1, 2, 4])
+def test_prism_vacuum_closed_form(P, f):
+    import torch
+    say(f"prism vacuum f={f}")
+    n, L = 128, 16.0
+    g = P.prism_grid_init((L, L, 4.0), 2.0, n)
+    d = P.prism_smatrix_plan(g, 80e3, 0.02, f)
+    V = torch.zeros((g.n_slices, n, n), dtype=torch.float32, device="cuda")
+    Sg = P.prism_build_smatrix(d, V)
+    xy = W.scan_positions((L, L), 3, 5)
+    out = P.prism_probe_outputs(d, Sg, P.prism_probe_plan_upload(d, xy), P.PRISM_FP32).cpu().numpy()
+    beams = O.beam_set(n, L, d.lambda_, 0.02, f)
+    ang = np.array([d.lambda_ * math.hypot(kx, ky) / L for kx, ky in beams])
+    exp = np.bincount(np.floor(ang / 1e-3).astype(int), minlength=out.shape[1])[:out.shape[1]] / len(beams)
+    assert np.max(np.abs(out - exp[None, :])) <= 2e-6
+
+
+# --------------------------------------------------------------- multislice --
+@pytest.mark.parametrize("n,scan,seed", [(64, (3, 3), 0), (128, (2, 3), 3), (256, (2, 2), 4)])
+def test_multislice_end_to_end_small(P, n, scan, seed):
+    say(f"multislice e2e n={n} scan={scan}")
+    cell = (10.0 * n / 64, 10.0 * n / 64, 6.0)
+    w, pos, sp = W.small_workload(n=n, cell=cell, n_atoms=int(12 * (n / 64) ** 2), scan=scan, seed=seed)
+    g, V = _gpu_potential(P, w, pos, sp)
+    xy = W.scan_positions(w.cell, *scan)
+    out = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=4)
+    _sync()
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    ref = O.multislice_outputs(Vref, w.cell[0], w.dz, O.wavelength(w.E0), O.interaction_constant(w.E0),
+                               w.alpha_max, xy)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "multislice")
+
+
+def test_prism_f1_matches_oracle_multislice(P):
+    say("prism f=1 vs oracle multislice n=64")
+    w, pos, sp = W.small_workload(n=64, n_atoms=16, seed=5, f=1)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, 1)
+    Sg = P.prism_build_smatrix(d, V)
+    xy = np.array([[0.0, 0.0], [2.5, 7.5], [6.1, 3.9], [9.7, 9.7]])
+    out = P.prism_probe_outputs(d, Sg, P.prism_probe_plan_upload(d, xy), P.PRISM_FP32)
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    ref = O.multislice_outputs(Vref, w.cell[0], w.dz, d.lambda_, d.sigma, w.alpha_max, xy)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "prism f=1 vs multislice")
+
+
+# ------------------------------------------------------------------ config 0 --
+def test_config0_prism_and_multislice_full(P):
+    """Config 0 in full: PRISM f=2 (256 probes) and multislice on the same cell."""
+    say("config0 full prism f=2 + multislice")
+    w = W.CONFIGS[0]
+    pos, sp = W.atoms_for(w)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    Sg = P.prism_build_smatrix(d, V)
+    xy = W.scan_positions(w.cell, *w.scan)
+    out = P.prism_probe_outputs(d, Sg, P.prism_probe_plan_upload(d, xy), P.PRISM_FP32)
+    ms = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy[::17], batch=16)
+    _sync()
+    L = w.cell[0]
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    beams = O.beam_set(w.n, L, d.lambda_, w.alpha_max, w.f)
+    Sref = O.build_smatrix(Vref, L, w.dz, d.lambda_, d.sigma, beams)
+    assert np.max(np.abs(Sg.cpu().numpy() - Sref)) <= TOL * np.max(np.abs(Sref))
+    ref = O.prism_outputs(Sref, beams, L, w.n, d.lambda_, w.f, xy)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "config0 prism")
+    mref = O.multislice_outputs(Vref, L, w.dz, d.lambda_, d.sigma, w.alpha_max, xy[::17])
+    _check_D(ms.cpu().numpy().astype(np.float64), mref, "config0 multislice")
