@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""PRISM benchmark on one MI355X.
+
+Workload: PRISM f=4 on the 100 x 100 x 100 A nanoparticle-in-amorphous cell,
+1024 x 1024 grid, 2 A slices (50), 200 keV, 20 mrad, 1245 beams, 128 x 128
+probe scan, 1-mrad annular bins.  One step = the whole hot path on resident
+inputs: compact S-matrix build (transmission, 50 x row/column propagation
+passes, real-space store) followed by synthesis of all 16384 probes
+(coefficients, windowed contraction, window FFT, detector sums).
+
+Prints one JSON line.  `value` is probe positions per second of whole steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+
+METRIC = "probe positions/s + S-matrix beams/s @1024², ≤1e-4 rel err vs FP64; p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp32", "bf16x3", "bf16"], default="fp32")
+    ap.add_argument("--config", type=int, default=2, help="workload index (2: PRISM f=4 @1024^2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-beams", type=int, default=3)
+    ap.add_argument("--cpu-probes", type=int, default=12)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, d, n_beams, n_probes, args):
+    """Time the FP64 oracle on a bounded sample of the same workload.
+
+    Multislice propagation and window synthesis cost does not depend on the
+    values, so the sample uses seeded random inputs of the workload's shape:
+    `cpu_beams` S-matrix layers (50 slices each) and `cpu_probes` probe
+    syntheses over all beams; the step time is extrapolated to every beam and
+    every probe of the scan.
+    """
+    import numpy as np
+    import oracle as O
+    import workloads as W
+
+    rng = np.random.default_rng(1234)
+    n, L = w.n, w.cell[0]
+    V = rng.uniform(0.0, 60.0, size=(w.n_slices, n, n))
+    t = O.transmission(V, d.sigma)
+    Pp = O.propagator(n, L, d.lambda_, w.dz)
+    beams = O.beam_set(n, L, d.lambda_, w.alpha_max, w.f)
+    t0 = time.perf_counter()
+    for b in range(args.cpu_beams):
+        O.smatrix_layer(t, Pp, int(beams[b, 0]), int(beams[b, 1]))
+    t_beam = (time.perf_counter() - t0) / args.cpu_beams
+    M = d.m_win
+    S = W.random_complex((len(beams), M, M), rng)
+    xy = W.scan_positions(w.cell, *w.scan, sub=max(1, w.scan[0] // 4))[: args.cpu_probes]
+    t0 = time.perf_counter()
+    O.prism_outputs(S, beams, L, n, d.lambda_, w.f, xy)
+    t_probe = (time.perf_counter() - t0) / len(xy)
+    step = n_beams * t_beam + n_probes * t_probe
+    return {"value": n_probes / step, "unit": "probe positions/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"{args.cpu_beams} S-matrix layers ({w.n_slices} slices, {n}^2, FP64) at "
+                      f"{t_beam:.3f} s/beam and {len(xy)} probe syntheses ({n_beams} beams, {M}^2 window) at "
+                      f"{t_probe:.3f} s/probe, extrapolated to {n_beams} beams + {n_probes} probes "
+                      f"= {step:.0f} s per step",
+            "beams_per_s": 1.0 / t_beam}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "detail": "multi-GPU sharding is described in the design notes, not implemented"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1706_08563_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
+
+    w = W.CONFIGS[args.config]
+    log(f"workload {w.name}: setup")
+    pos, sp = W.atoms_for(w)
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    V = P.prism_project_potential(pos, sp, w.species, g)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    xy = W.scan_positions(w.cell, *w.scan)
+    t0 = time.perf_counter()
+    plan = P.prism_probe_plan_upload(d, xy)
+    plan_s = time.perf_counter() - t0
+    B, n, nsl, M = d.n_beams, w.n, g.n_slices, d.m_win
+    n_probes = len(xy)
+    ws_build = torch.empty(d.build_ws_bytes, dtype=torch.uint8, device=dev)
+    ws_probe = torch.empty(plan.plan.ws_bytes, dtype=torch.uint8, device=dev)
+    S = torch.empty((B, d.ns, d.ns), dtype=torch.complex64, device=dev)
+    out = torch.empty((n_probes, plan.plan.n_bins), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def build():
+        P.prism_build_smatrix(d, V, ws=ws_build, S=S)
+
+    def synth():
+        P.prism_probe_outputs(d, S, plan, prec, ws=ws_probe, out=out)
+
+    log(f"warmup {args.warmup} (beams {B}, slices {nsl}, probes {n_probes}, window {M})")
+    for _ in range(args.warmup):
+        build()
+        synth()
+    torch.cuda.synchronize()
+
+    log(f"timed {args.steps} steps")
+    P.prism_timing_reset()
+    P.prism_timing_enable(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        build()
+        ev[i][1].record(stream)
+        synth()
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    P.prism_timing_enable(False)
+    step_ms = [a.elapsed_time(c) for a, b, c in ev]
+    build_ms = [a.elapsed_time(b) for a, b, c in ev]
+    synth_ms = [b.elapsed_time(c) for a, b, c in ev]
+    kt = {name: P.prism_timing_read(cls) for name, cls in P.TIMING_CLASSES.items()}
+    log(f"steps done: wall {wall:.3f} s; step ms {step_ms}")
+
+    ms_per_step = wall * 1e3 / args.steps
+    N2 = float(n) * n
+    # algorithmic HBM bytes per launch of the propagation passes (band-limited
+    # wave: 4 N^2 B per beam read and written, plus the slice's transmission)
+    a_bytes = (B * 8 * N2 * (nsl - 1) + B * 4 * N2 + nsl * 8 * N2) / nsl
+    b_bytes = (B * 8 * N2 * (nsl - 1) + B * 6 * N2) / nsl
+    c_flops = 8.0 * B * M * M * n_probes          # useful complex MACs x 8
+    kernels = {}
+    for name, (tot, cnt) in kt.items():
+        if cnt:
+            kernels[name] = {"ms_total": tot / args.steps, "launches_per_step": cnt // args.steps,
+                             "avg_ms": tot / cnt}
+    kernels["pass_a"]["GB_per_s"] = a_bytes / (kernels["pass_a"]["avg_ms"] * 1e-3) / 1e9
+    kernels["pass_b"]["GB_per_s"] = b_bytes / (kernels["pass_b"]["avg_ms"] * 1e-3) / 1e9
+    kernels["contract"]["TFLOP_per_s"] = c_flops / (kernels["contract"]["avg_ms"] * 1e-3) / 1e12
+    dom = max(["pass_a", "pass_b", "contract"], key=lambda k: kernels[k]["ms_total"])
+    if dom == "contract":
+        peak = PEAK_FP32_TFLOPS if prec == P.PRISM_FP32 else PEAK_BF16_TFLOPS
+        ach = kernels["contract"]["TFLOP_per_s"]
+        roof = {"kernel": "contract", "bound": "alu" if prec == P.PRISM_FP32 else "mfma", "achieved": ach,
+                "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None}
+    else:
+        ach = kernels[dom]["GB_per_s"]
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None}
+
+    res = {
+        "metric": METRIC,
+        "value": n_probes / (ms_per_step * 1e-3),
+        "unit": "probe positions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == P.PRISM_FP32 else ("bf16x3/f32" if prec == P.PRISM_SPLIT_BF16X3 else "bf16/f32"),
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": n, "cell_A": list(w.cell), "slices": nsl, "E0_eV": w.E0,
+                   "alpha_mrad": w.alpha_max * 1e3, "f": w.f, "beams": B, "probes": n_probes, "window": M,
+                   "n_bins": plan.plan.n_bins, "precision": args.precision},
+        "beams_per_s": B / (float(np.median(build_ms)) * 1e-3),
+        "probes_per_s_synthesis": n_probes / (float(np.median(synth_ms)) * 1e-3),
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "build_ms": float(np.median(build_ms)),
+        "synthesis_ms": float(np.median(synth_ms)),
+        "probe_plan_host_s": plan_s,
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle, bounded sample)")
+        res["cpu_baseline"] = cpu_baseline(w, d, B, n_probes, args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -204,6 +204,28 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
 int prism_detector_bin_map(double lambda, double Lw, double alpha_aa, double dalpha,
                            int32_t n_bins, int32_t m, int32_t* map);
 
+/* ---- kernel timing (diagnostics) --------------------------------------------- */
+
+#define PRISM_K_PASS_A         0   /* row pass: inverse row DFT, transmission, forward row DFT */
+#define PRISM_K_PASS_B         1   /* column pass: forward column DFT, propagator, inverse column DFT */
+#define PRISM_K_FINAL          2   /* S-matrix real-space store */
+#define PRISM_K_TRANSMISSION   3   /* exp(i sigma V) */
+#define PRISM_K_COEFFICIENTS   4   /* probe coefficients */
+#define PRISM_K_CONTRACT       5   /* windowed beam contraction */
+#define PRISM_K_WINDOW         6   /* window FFT, |Psi|^2, detector sums */
+#define PRISM_K_POTENTIAL      7   /* projected potential */
+#define PRISM_K_BIN_REDUCE     8   /* multislice detector sums */
+#define PRISM_TIMING_CLASSES   9
+
+/* While enabled (per calling thread), every kernel launch of the library is
+ * bracketed by HIP events recorded on its stream. */
+int prism_timing_enable(int32_t enable);
+/* Drop pending events and zero the totals of the calling thread. */
+int prism_timing_reset(void);
+/* Total device milliseconds and launch count of kernel class `cls` since the
+ * last reset; waits for the recorded events.  Errors: PRISM_E_INVAL, PRISM_E_DEVICE. */
+int prism_timing_read(int32_t cls, double* total_ms, int64_t* launches);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* prism_last_error(void);
 

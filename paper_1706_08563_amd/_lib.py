@@ -72,7 +72,13 @@ _SIGNATURES = {
     "multislice_outputs": ([POINTER(prism_grid), c_double, c_double, c_void_p, c_void_p, c_int64, c_double, c_int32,
                             c_int32, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "prism_detector_bin_map": ([c_double, c_double, c_double, c_double, c_int32, c_int32, c_void_p], c_int32),
+    "prism_timing_enable": ([c_int32], c_int32),
+    "prism_timing_reset": ([], c_int32),
+    "prism_timing_read": ([c_int32, POINTER(c_double), POINTER(c_int64)], c_int32),
 }
+
+TIMING_CLASSES = {"pass_a": 0, "pass_b": 1, "final": 2, "transmission": 3, "coefficients": 4, "contract": 5,
+                  "window": 6, "potential": 7, "bin_reduce": 8}
 
 EXPORTED = tuple(_SIGNATURES)
 

@@ -91,10 +91,11 @@ def prism_project_potential(pos, species_idx, species, grid: prism_grid, device=
     return V
 
 
-def prism_build_smatrix(d: prism_smatrix_desc, V, ws=None):
+def prism_build_smatrix(d: prism_smatrix_desc, V, ws=None, S=None):
     """S [n_beams, n/2, n/2] complex64 on the device."""
     torch = _torch()
-    S = torch.empty((d.n_beams, d.ns, d.ns), dtype=torch.complex64, device=V.device)
+    if S is None:
+        S = torch.empty((d.n_beams, d.ns, d.ns), dtype=torch.complex64, device=V.device)
     if ws is None:
         ws = _workspace(d.build_ws_bytes, V.device)
     check(lib.prism_build_smatrix(ctypes.byref(d), _dev(V), _dev(S), _dev(ws), ws.numel(), _stream()))
@@ -164,3 +165,20 @@ def multislice_outputs(grid: prism_grid, E0: float, alpha_max: float, V, xy, dal
                                  xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha), int(n_bins), int(batch),
                                  _dev(out), _dev(ws), ws.numel(), _stream()))
     return out
+
+
+# ---------------------------------------------------------------- timing --
+def prism_timing_enable(enable: bool = True):
+    check(lib.prism_timing_enable(1 if enable else 0))
+
+
+def prism_timing_reset():
+    check(lib.prism_timing_reset())
+
+
+def prism_timing_read(cls: int):
+    """(total device ms, launches) of kernel class `cls` since the last reset."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    check(lib.prism_timing_read(int(cls), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

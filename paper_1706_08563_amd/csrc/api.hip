@@ -43,6 +43,34 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(PRISM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// ------------------------------------------------------- kernel timing --
+// Optional per-kernel-class timing: when enabled on the calling thread, each
+// launch is bracketed by HIP events on its stream.  Totals are read after the
+// caller has synchronised the stream.
+struct TimedLaunch {
+    int cls;
+    hipEvent_t a, b;
+};
+thread_local bool t_timing = false;
+thread_local std::vector<TimedLaunch> t_pending;
+thread_local double t_total_ms[PRISM_TIMING_CLASSES];
+thread_local int64_t t_count[PRISM_TIMING_CLASSES];
+
+template <class Fn>
+hipError_t timed(int cls, hipStream_t st, Fn&& fn) {
+    if (!t_timing) return fn();
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e == hipSuccess) t_pending.push_back(TimedLaunch{cls, a, b});
+    return e;
+}
+
 // ---------------------------------------------------------------- physics --
 // Relativistic wavelength and interaction constant of Eqs. (1)-(2), CODATA 2018.
 constexpr double kPlanck = 6.62607015e-34, kLight = 299792458.0, kCharge = 1.602176634e-19,
@@ -387,7 +415,7 @@ int prism_project_potential(const prism_atom* atoms, int64_t n_atoms, const pris
     hipStream_t st = as_stream(stream);
     rc = upload(ws, blob, st);
     if (rc) return rc;
-    HIP_TRY(launch_potential(V, grid->n, S, L, d_atoms, d_start, d_sp, rc_max, st));
+    HIP_TRY(timed(PRISM_K_POTENTIAL, st, [&] { return launch_potential(V, grid->n, S, L, d_atoms, d_start, d_sp, rc_max, st); }));
     return PRISM_OK;
 }
 
@@ -459,13 +487,15 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     rc = upload(ws, blob, st);
     if (rc) return rc;
     const PropTables tb = pd.tables();
-    HIP_TRY(launch_transmission(V, T, (int64_t)nsl * n * n, (float)d->sigma, st));
+    HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(V, T, (int64_t)nsl * n * n, (float)d->sigma, st); }));
     for (int s = 0; s < nsl; ++s) {
-        HIP_TRY(launch_pass_a(n, W, T + (size_t)s * n * n, tb, d_beams, s == 0, B, st));
-        HIP_TRY(launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, W, tb, nullptr, nullptr, nullptr, nullptr,
-                              0.0, 0.f, B, st));
+        HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, W, T + (size_t)s * n * n, tb, d_beams, s == 0, B, st); }));
+        HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
+            return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, W, tb, nullptr, nullptr, nullptr, nullptr,
+                                 0.0, 0.f, B, st);
+        }));
     }
-    HIP_TRY(launch_smatrix_final(n, W, static_cast<float2*>(S), pd.tw_half, B, st));
+    HIP_TRY(timed(PRISM_K_FINAL, st, [&] { return launch_smatrix_final(n, W, static_cast<float2*>(S), pd.tw_half, B, st); }));
     return PRISM_OK;
 }
 
@@ -559,10 +589,16 @@ int prism_probe_outputs(const prism_smatrix_desc* d, const void* S, const prism_
     float2* C = c.take<float2>((size_t)P * B);
     float2* win = c.take<float2>((size_t)P * M * M);
     hipStream_t st = as_stream(stream);
-    HIP_TRY(launch_coefficients(C, xy, beams, P, B, 1.0 / d->grid.cell[0], (float)(1.0 / std::sqrt((double)B)), st));
-    HIP_TRY(launch_contract(precision, C, static_cast<const float2*>(S), win, tstart, tprobes, corner, plan->n_tiles,
-                            plan->max_per_tile, B, d->ns, M, st));
-    HIP_TRY(launch_window_detect(M, win, out, perm, bstart, tw_m, P, plan->n_bins, st));
+    HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
+        return launch_coefficients(C, xy, beams, P, B, 1.0 / d->grid.cell[0], (float)(1.0 / std::sqrt((double)B)), st);
+    }));
+    HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] {
+        return launch_contract(precision, C, static_cast<const float2*>(S), win, tstart, tprobes, corner,
+                               plan->n_tiles, plan->max_per_tile, B, d->ns, M, st);
+    }));
+    HIP_TRY(timed(PRISM_K_WINDOW, st, [&] {
+        return launch_window_detect(M, win, out, perm, bstart, tw_m, P, plan->n_bins, st);
+    }));
     return PRISM_OK;
 }
 
@@ -670,18 +706,60 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
     rc = upload(ws, blob, st);
     if (rc) return rc;
     const PropTables tb = pd.tables();
-    HIP_TRY(launch_transmission(V, T, (int64_t)nsl * n * n, (float)sig, st));
+    HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(V, T, (int64_t)nsl * n * n, (float)sig, st); }));
     const float amp = (float)(1.0 / std::sqrt((double)n_ap));
     for (int64_t p0 = 0; p0 < n_probes; p0 += batch) {
         const int nb = (int)std::min<int64_t>(batch, n_probes - p0);
-        HIP_TRY(launch_pass_b(n, PASSB_INIT, W, tb, nullptr, nullptr, d_kymax, d_xy + p0, 1.0 / L, amp, nb, st));
+        HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
+            return launch_pass_b(n, PASSB_INIT, W, tb, nullptr, nullptr, d_kymax, d_xy + p0, 1.0 / L, amp, nb, st);
+        }));
         for (int s = 0; s < nsl; ++s) {
-            HIP_TRY(launch_pass_a(n, W, T + (size_t)s * n * n, tb, nullptr, false, nb, st));
-            HIP_TRY(launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_I : PASSB_MID, W, tb, nullptr, I, nullptr, nullptr,
-                                  0.0, 0.f, nb, st));
+            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, W, T + (size_t)s * n * n, tb, nullptr, false, nb, st); }));
+            HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
+                return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_I : PASSB_MID, W, tb, nullptr, I, nullptr, nullptr,
+                                     0.0, 0.f, nb, st);
+            }));
         }
-        HIP_TRY(launch_bin_reduce(I, (int64_t)Lh * Lh, out + p0 * n_bins, d_perm, d_bstart, nb, n_bins, st));
+        HIP_TRY(timed(PRISM_K_BIN_REDUCE, st, [&] {
+            return launch_bin_reduce(I, (int64_t)Lh * Lh, out + p0 * n_bins, d_perm, d_bstart, nb, n_bins, st);
+        }));
     }
+    return PRISM_OK;
+}
+
+int prism_timing_enable(int32_t enable) {
+    t_timing = enable != 0;
+    return PRISM_OK;
+}
+
+int prism_timing_reset(void) {
+    for (auto& r : t_pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    t_pending.clear();
+    for (int i = 0; i < PRISM_TIMING_CLASSES; ++i) {
+        t_total_ms[i] = 0.0;
+        t_count[i] = 0;
+    }
+    return PRISM_OK;
+}
+
+int prism_timing_read(int32_t cls, double* total_ms, int64_t* launches) {
+    if (cls < 0 || cls >= PRISM_TIMING_CLASSES || !total_ms || !launches)
+        return fail(PRISM_E_INVAL, "timing: invalid argument");
+    for (auto& r : t_pending) {
+        float ms = 0.f;
+        HIP_TRY(hipEventSynchronize(r.b));
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        t_total_ms[r.cls] += ms;
+        t_count[r.cls] += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    t_pending.clear();
+    *total_ms = t_total_ms[cls];
+    *launches = t_count[cls];
     return PRISM_OK;
 }
 
