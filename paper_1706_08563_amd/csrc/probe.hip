@@ -115,14 +115,203 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(const float2* __restrict__
     }
 }
 
+// ----------------------------------------------- MFMA (BF16) contraction --
+// The complex product is carried by real BF16 MFMA (v_mfma_f32_16x16x32_bf16)
+// through the block identity, with K running over 16 beams twice:
+//   Re = [Cr | -Ci] . [Sr ; Si]        Im = [Ci | Cr] . [Sr ; Si]
+// Split mode: every FP32 operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi),
+// and each product is hi*hi + hi*lo + lo*hi accumulated in FP32 (the lo*lo
+// term, ~2^-16 relative, is dropped).  Plain mode keeps hi*hi only.
+//
+// Workgroup: one 16 x 16 pixel tile x 64 probes.  Wave w owns tile rows
+// 4w..4w+3 (four 16-pixel MFMA column blocks) and all four 16-probe row blocks.
+namespace mfmac {
+constexpr int PC = 64;   // probes per workgroup
+constexpr int KB = 16;   // beams per K step
+}
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_to_f32(hi));
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+template <bool SPLIT>
+__global__ __launch_bounds__(WG) void k_contract_mfma(const float2* __restrict__ C, const float2* __restrict__ S,
+                                                      float2* __restrict__ win, const int* __restrict__ tile_start,
+                                                      const int* __restrict__ tile_probes,
+                                                      const int2* __restrict__ corner, int n_beams, int ns, int m) {
+    using namespace mfmac;
+    constexpr int NP = SPLIT ? 2 : 1;           // hi (, lo)
+    // [part][re/im][row][beam]: 16 beams of a row contiguous (32 B)
+    __shared__ __attribute__((aligned(16))) unsigned short Ss[NP][2][256][KB];
+    __shared__ __attribute__((aligned(16))) unsigned short Cs[NP][2][PC][KB];
+    __shared__ int pidx[PC];
+
+    const int tile = blockIdx.x;
+    const int t0 = tile_start[tile], t1 = tile_start[tile + 1];
+    const int pc0 = t0 + (int)blockIdx.y * PC;
+    if (pc0 >= t1) return;
+    const int np = min(PC, t1 - pc0);
+    const int ntx = ns / TILE;
+    const int tx0 = (tile % ntx) * TILE, ty0 = (tile / ntx) * TILE;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid < PC) pidx[tid] = tid < np ? tile_probes[pc0 + tid] : -1;
+
+    f32x4 accr[4][4], acci[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            accr[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            acci[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    const size_t plane = (size_t)ns * ns;
+    // S staging: thread = one tile pixel
+    const int spix = tid;
+    const float2* Sp = S + (size_t)(ty0 + spix / TILE) * ns + tx0 + (spix % TILE);
+    // C staging: thread = (probe, 4 beams)
+    const int cp = tid >> 2, cb = (tid & 3) * 4;
+    __syncthreads();
+    const int cq = pidx[cp];
+
+    const int col = lane & 15, g = lane >> 4;   // MFMA operand lane roles
+    for (int b0 = 0; b0 < n_beams; b0 += KB) {
+        // ---- stage S: 16 beams of this pixel
+        {
+            unsigned short hr[KB], hi_[KB], lr[KB], li[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                float2 v = (b0 + k < n_beams) ? Sp[(size_t)(b0 + k) * plane] : make_float2(0.f, 0.f);
+                if constexpr (SPLIT) {
+                    split_bf16(v.x, hr[k], lr[k]);
+                    split_bf16(v.y, hi_[k], li[k]);
+                } else {
+                    hr[k] = bf16_rne(v.x);
+                    hi_[k] = bf16_rne(v.y);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                Ss[0][0][spix][k] = hr[k];
+                Ss[0][1][spix][k] = hi_[k];
+                if constexpr (SPLIT) {
+                    Ss[NP - 1][0][spix][k] = lr[k];
+                    Ss[NP - 1][1][spix][k] = li[k];
+                }
+            }
+        }
+        // ---- stage C: 4 beams of one probe
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int b = b0 + cb + k;
+            float2 v = (cq >= 0 && b < n_beams) ? C[(size_t)cq * n_beams + b] : make_float2(0.f, 0.f);
+            if constexpr (SPLIT) {
+                unsigned short a0, a1, a2, a3;
+                split_bf16(v.x, a0, a1);
+                split_bf16(v.y, a2, a3);
+                Cs[0][0][cp][cb + k] = a0;
+                Cs[NP - 1][0][cp][cb + k] = a1;
+                Cs[0][1][cp][cb + k] = a2;
+                Cs[NP - 1][1][cp][cb + k] = a3;
+            } else {
+                Cs[0][0][cp][cb + k] = bf16_rne(v.x);
+                Cs[0][1][cp][cb + k] = bf16_rne(v.y);
+            }
+        }
+        __syncthreads();
+        // ---- B operands: pixel block pb = tile row 4*wave + pb, lane column = pixel
+        //      k-group g: 0,1 -> Sr beams 8g.., 2,3 -> Si beams 8(g-2)..
+        u32x4 Bop[NP][4];
+#pragma unroll
+        for (int part = 0; part < NP; ++part)
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const int pix = (4 * wave + pb) * TILE + col;
+                Bop[part][pb] = *reinterpret_cast<const u32x4*>(&Ss[part][g >> 1][pix][8 * (g & 1)]);
+            }
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+            const int prow = 16 * qb + col;
+            // A_r = [Cr | -Ci], A_i = [Ci | Cr]
+            u32x4 Ar[NP], Ai[NP];
+#pragma unroll
+            for (int part = 0; part < NP; ++part) {
+                u32x4 cr = *reinterpret_cast<const u32x4*>(&Cs[part][0][prow][8 * (g & 1)]);
+                u32x4 ci = *reinterpret_cast<const u32x4*>(&Cs[part][1][prow][8 * (g & 1)]);
+                if (g < 2) {
+                    Ar[part] = cr;
+                    Ai[part] = ci;
+                } else {
+                    Ar[part] = ci ^ u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+                    Ai[part] = cr;
+                }
+            }
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                accr[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ar[0]), as_bf16x8(Bop[0][pb]),
+                                                                      accr[qb][pb], 0, 0, 0);
+                acci[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ai[0]), as_bf16x8(Bop[0][pb]),
+                                                                      acci[qb][pb], 0, 0, 0);
+                if constexpr (SPLIT) {
+                    accr[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ar[0]), as_bf16x8(Bop[1][pb]),
+                                                                          accr[qb][pb], 0, 0, 0);
+                    acci[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ai[0]), as_bf16x8(Bop[1][pb]),
+                                                                          acci[qb][pb], 0, 0, 0);
+                    accr[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ar[1]), as_bf16x8(Bop[0][pb]),
+                                                                          accr[qb][pb], 0, 0, 0);
+                    acci[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ai[1]), as_bf16x8(Bop[0][pb]),
+                                                                          acci[qb][pb], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // ---- epilogue: D row = probe 16 qb + 4 g + r, column = pixel
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = pidx[16 * qb + 4 * g + r];
+            if (q < 0) continue;
+            const int2 c0 = corner[q];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const int py = ty0 + 4 * wave + pb, px = tx0 + col;
+                const int v = (py - c0.y) & (ns - 1);
+                const int u = (px - c0.x) & (ns - 1);
+                if (v < m && u < m) win[(size_t)q * m * m + (size_t)v * m + u] = make_float2(accr[qb][pb][r], acci[qb][pb][r]);
+            }
+        }
+}
+
 hipError_t launch_contract(int precision, const float2* C, const float2* S, float2* win, const int* tile_start,
                            const int* tile_probes, const int2* corner, int n_tiles, int max_per_tile, int n_beams,
                            int ns, int m, hipStream_t st) {
-    (void)precision;
-    using namespace fp32c;
-    dim3 grid((unsigned)n_tiles, (unsigned)((max_per_tile + PC - 1) / PC));
-    hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes, corner, n_beams,
-                       ns, m);
+    if (precision == 0) {
+        using namespace fp32c;
+        dim3 grid((unsigned)n_tiles, (unsigned)((max_per_tile + PC - 1) / PC));
+        hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes, corner,
+                           n_beams, ns, m);
+    } else {
+        dim3 grid((unsigned)n_tiles, (unsigned)((max_per_tile + mfmac::PC - 1) / mfmac::PC));
+        if (precision == 1)
+            hipLaunchKernelGGL(k_contract_mfma<true>, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes,
+                               corner, n_beams, ns, m);
+        else
+            hipLaunchKernelGGL(k_contract_mfma<false>, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes,
+                               corner, n_beams, ns, m);
+    }
     return hipGetLastError();
 }
 

@@ -118,24 +118,34 @@ def test_prism_end_to_end_small(P, n, f, scan, seed):
     _check_D(out.cpu().numpy().astype(np.float64), ref, "fp32")
 
 
-def test_prism_synthesis_random_smatrix(P):
-    """Probe synthesis alone on a seeded random S-matrix, random probe positions."""
+PRECISIONS = [("fp32", 0, TOL), ("bf16x3", 1, TOL), ("bf16", 2, None)]
+
+
+@pytest.mark.parametrize("name,prec,tol", PRECISIONS)
+@pytest.mark.parametrize("n,L,f", [(256, 20.0, 2), (512, 40.0, 4), (1024, 100.0, 8)])
+def test_prism_synthesis_random_smatrix(P, name, prec, tol, n, L, f):
+    """Probe synthesis alone on a seeded random S-matrix, random probe positions
+    (ragged tile counts, windows wrapping the periodic edge), each precision."""
     import torch
-    say("prism synthesis random S n=256 f=2 random probes")
-    n, L, f = 256, 20.0, 2
+    say(f"prism synthesis random S n={n} f={f} precision={name}")
     g = P.prism_grid_init((L, L, 2.0), 2.0, n)
-    d = P.prism_smatrix_plan(g, 80e3, 0.02, f)
-    rng = np.random.default_rng(11)
+    d = P.prism_smatrix_plan(g, 200e3, 0.02, f)
+    rng = np.random.default_rng(11 + n)
     S = W.random_complex((d.n_beams, d.ns, d.ns), rng)
     xy = np.concatenate([W.random_positions((L, L), 37, rng), [[0.0, 0.0], [L - 1e-9, L - 1e-9], [-3.0, 25.0]]])
     plan = P.prism_probe_plan_upload(d, xy)
-    out = P.prism_probe_outputs(d, torch.tensor(S, device="cuda"), plan, P.PRISM_FP32)
+    out = P.prism_probe_outputs(d, torch.tensor(S, device="cuda"), plan, prec)
     _sync()
     beams = O.beam_set(n, L, d.lambda_, 0.02, f)
     ref = O.prism_outputs(S.astype(np.complex128), beams, L, n, d.lambda_, f, xy)
     got = out.cpu().numpy().astype(np.float64)
-    assert O.rel_err(got, ref) <= TOL
-    assert np.max(np.abs(got - ref) / (np.abs(ref) + 1e-3 * np.abs(ref).max())) <= 10 * TOL
+    err = O.rel_err(got, ref)
+    say(f"  {name}: rel_all={err:.3e}")
+    if tol is None:
+        assert err < 0.05          # plain BF16: reported, loosely bounded
+    else:
+        assert err <= tol
+        assert np.max(np.abs(got - ref) / (np.abs(ref) + 1e-3 * np.abs(ref).max())) <= 10 * tol
 
 
 # ------------------------------------------------------------------ vacuum --
@@ -195,7 +205,9 @@ def test_config0_prism_and_multislice_full(P):
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
     Sg = P.prism_build_smatrix(d, V)
     xy = W.scan_positions(w.cell, *w.scan)
-    out = P.prism_probe_outputs(d, Sg, P.prism_probe_plan_upload(d, xy), P.PRISM_FP32)
+    plan = P.prism_probe_plan_upload(d, xy)
+    out = P.prism_probe_outputs(d, Sg, plan, P.PRISM_FP32)
+    out3 = P.prism_probe_outputs(d, Sg, plan, P.PRISM_SPLIT_BF16X3)
     ms = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy[::17], batch=16)
     _sync()
     L = w.cell[0]
@@ -205,5 +217,6 @@ def test_config0_prism_and_multislice_full(P):
     assert np.max(np.abs(Sg.cpu().numpy() - Sref)) <= TOL * np.max(np.abs(Sref))
     ref = O.prism_outputs(Sref, beams, L, w.n, d.lambda_, w.f, xy)
     _check_D(out.cpu().numpy().astype(np.float64), ref, "config0 prism")
+    _check_D(out3.cpu().numpy().astype(np.float64), ref, "config0 prism split-bf16")
     mref = O.multislice_outputs(Vref, L, w.dz, d.lambda_, d.sigma, w.alpha_max, xy[::17])
     _check_D(ms.cpu().numpy().astype(np.float64), mref, "config0 multislice")
