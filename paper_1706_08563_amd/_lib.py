@@ -8,7 +8,8 @@ import os
 from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p, c_char_p
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libprism.so")
+# PRISM_LIBRARY selects another build of the same library (A/B comparisons).
+LIB_PATH = os.environ.get("PRISM_LIBRARY") or os.path.join(_HERE, "libprism.so")
 
 PRISM_OK = 0
 PRISM_E_INVAL = -1

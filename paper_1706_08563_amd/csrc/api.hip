@@ -445,7 +445,7 @@ int prism_smatrix_plan(prism_smatrix_desc* d) {
     carve_prop(c, n);
     c.take<int2>(d->n_beams);
     c.take<float2>((size_t)d->grid.n_slices * n * n);
-    c.take<float2>((size_t)d->n_beams * (n / 2) * n);
+    c.take<float2>((size_t)d->n_beams * (n / 2) * wave_col_stride(n));
     d->build_ws_bytes = c.off + 256;
     return PRISM_OK;
 }
@@ -476,7 +476,7 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     PropDev pd = carve_prop(c, n);
     int2* d_beams = c.take<int2>(B);
     float2* T = c.take<float2>((size_t)nsl * n * n);
-    float2* W = c.take<float2>((size_t)B * (n / 2) * n);
+    float2* W = c.take<float2>((size_t)B * (n / 2) * wave_col_stride(n));
     PropHost ph = prop_tables(n, L, d->lambda, d->grid.dz);
     std::vector<char> blob;
     stage(blob, ws, pd.tw_half, ph.tw_half);
@@ -612,7 +612,7 @@ static void multislice_carve(Carve& c, int n, int nsl, int64_t n_probes, int bat
     bstart = c.take<int>(n_bins + 1);
     xy = c.take<double2>((size_t)std::max<int64_t>(n_probes, 1));
     T = c.take<float2>((size_t)nsl * n * n);
-    W = c.take<float2>((size_t)batch * (n / 2) * n);
+    W = c.take<float2>((size_t)batch * (n / 2) * wave_col_stride(n));
     I = c.take<float>((size_t)batch * (n / 2) * (n / 2));
 }
 

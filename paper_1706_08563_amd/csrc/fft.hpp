@@ -220,6 +220,74 @@ struct Fft {
         }
     }
 
+    // Two independent transforms advanced stage by stage together, so the LDS
+    // round trip of one overlaps the arithmetic of the other.
+    template <int DIR, int S, class X>
+    __device__ __forceinline__ static void stage2(float2 (&v1)[E], float2 (&v2)[E], const X& x1, const X& x2,
+                                                  const Twiddles& tw, int lt) {
+        constexpr int R = radix(S), NS = ns(S), U = E / R;
+        float2 o1[E], o2[E];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float2 w1[R], w2[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                w1[r] = v1[u + r * U];
+                w2[r] = v2[u + r * U];
+            }
+            if constexpr (S > 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const float2 t = tw.w[tw_off(S) + u * (R - 1) + (r - 1)];
+                    w1[r] = ctw<DIR>(w1[r], t);
+                    w2[r] = ctw<DIR>(w2[r], t);
+                }
+            }
+            Dft<R, DIR>::run(w1);
+            Dft<R, DIR>::run(w2);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                o1[u * R + r] = w1[r];
+                o2[u * R + r] = w2[r];
+            }
+        }
+        if constexpr (S == NST - 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    v1[u + r * U] = o1[u * R + r];
+                    v2[u + r * U] = o2[u * R + r];
+                }
+        } else {
+            wave_sync();
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int j = lt + LPT * u;
+                int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    x1(base + r * NS) = o1[u * R + r];
+                    x2(base + r * NS) = o2[u * R + r];
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                v1[i] = x1(lt + LPT * i);
+                v2[i] = x2(lt + LPT * i);
+            }
+            stage2<DIR, S + 1>(v1, v2, x1, x2, tw, lt);
+        }
+    }
+
+    // Two transforms at once, each with its own padded exchange buffer.
+    template <int DIR>
+    __device__ __forceinline__ static void run2(float2 (&v1)[E], float2 (&v2)[E], float2* lds1, float2* lds2,
+                                                const Twiddles& tw, int lt) {
+        stage2<DIR, 0>(v1, v2, RowX{lds1}, RowX{lds2}, tw, lt);
+    }
+
     // In-place transform of the natural-order data v of lane lt (0..LPT-1);
     // lds: this transform's private exchange buffer (LDS entries padded).
     template <int DIR>

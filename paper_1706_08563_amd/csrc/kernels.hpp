@@ -8,7 +8,13 @@ namespace prism {
 // Band-limited wave buffer layout used by the propagation passes:
 //   W[item][j][y], j in [0, n/2) a band column (kx = j for j < n/4, j - n/2
 //   otherwise), y in [0, n) the real-space row.  One "item" is a beam
-//   (S-matrix) or a probe (multislice).
+//   (S-matrix) or a probe (multislice).  Columns are wave_col_stride(n) >= n
+//   elements apart so that the column starts do not all fall on the same
+//   power-of-two address stride.
+#ifndef PRISM_COL_PAD
+#define PRISM_COL_PAD 0
+#endif
+constexpr int wave_col_stride(int n) { return n + PRISM_COL_PAD; }
 struct PropTables {
     const float2* tw_half;   // W_{n/2}[m] = e^{-2 pi i m/(n/2)}, n/2 entries
     const float2* tw_full;   // W_n[m]     = e^{-2 pi i m/n},     n entries

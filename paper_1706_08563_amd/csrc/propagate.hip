@@ -24,6 +24,23 @@ namespace prism {
 
 constexpr int WG = 256;      // 4 wavefronts
 
+// Tuning constants (compile-time).
+#ifndef PRISM_PASSA_ROWS
+#define PRISM_PASSA_ROWS 16      // rows per pass-A workgroup for n <= 1024 (half that above)
+#endif
+#ifndef PRISM_PASSA_ILP
+#define PRISM_PASSA_ILP 0        // 1: even/odd row transforms advanced together (extra LDS)
+#endif
+#ifndef PRISM_PASSB_ILP
+#define PRISM_PASSB_ILP 0        // 1: even/odd column transforms advanced together
+#endif
+#ifndef PRISM_PASSA_WPE
+#define PRISM_PASSA_WPE 1        // minimum waves per SIMD asked of the register allocator
+#endif
+#ifndef PRISM_PASSB_WPE
+#define PRISM_PASSB_WPE 1
+#endif
+
 template <int N>
 struct RowCfg {
     static constexpr int L = N / 2;
@@ -31,9 +48,10 @@ struct RowCfg {
     static constexpr int E = F::E;
     static constexpr int LPT = F::LPT;
     static constexpr int G = 64 / LPT;                       // transforms per wave at once
-    static constexpr int TR0 = (N <= 1024) ? 16 : 8;         // rows per workgroup (tile height)
-    static constexpr int TR = TR0 > 4 * G ? TR0 : 4 * G;
+    static constexpr int TR0 = (N <= 1024) ? PRISM_PASSA_ROWS : PRISM_PASSA_ROWS / 2;
+    static constexpr int TR = TR0 > 4 * G ? TR0 : 4 * G;     // rows per workgroup (tile height)
     static constexpr int ROW = F::LDS + 1;                   // odd LDS row stride (float2)
+    static constexpr int XO = PRISM_PASSA_ILP ? 4 * G * F::LDS : 1;   // odd-transform buffers
 };
 
 // ------------------------------------------------------------ transmission --
@@ -57,22 +75,25 @@ hipError_t launch_transmission(const float* V, float2* T, int64_t count, float s
 
 // ------------------------------------------------------------------ pass A --
 template <int N, bool FIRST>
-__global__ __launch_bounds__(WG) void k_pass_a(float2* __restrict__ W, const float2* __restrict__ T, PropTables tb,
-                                               const int2* __restrict__ beams, int n_items) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_WPE))) void k_pass_a(
+    float2* __restrict__ W, const float2* __restrict__ T, PropTables tb, const int2* __restrict__ beams,
+    int n_items) {
     using C = RowCfg<N>;
     using F = typename C::F;
     constexpr int L = C::L, E = C::E, LPT = C::LPT, G = C::G, TR = C::TR, ROW = C::ROW;
     __shared__ float2 tile[TR * ROW];
+    __shared__ float2 xodd[C::XO];
 
     const int item = blockIdx.x % n_items;
     const int y0 = (blockIdx.x / n_items) * TR;
-    float2* Wi = W + (size_t)item * L * N;
+    constexpr int CS = wave_col_stride(N);
+    float2* Wi = W + (size_t)item * L * CS;
     const int tid = threadIdx.x;
 
     if constexpr (!FIRST) {
         for (int idx = tid; idx < L * TR; idx += WG) {
             int yy = idx % TR, j = idx / TR;
-            tile[yy * ROW + F::pad(j)] = Wi[(size_t)j * N + y0 + yy];
+            tile[yy * ROW + F::pad(j)] = Wi[(size_t)j * CS + y0 + yy];
         }
         __syncthreads();
     }
@@ -94,6 +115,14 @@ __global__ __launch_bounds__(WG) void k_pass_a(float2* __restrict__ W, const flo
     for (int r0 = wave * G; r0 < TR; r0 += 4 * G) {
         const int yy = r0 + g, y = y0 + yy;
         float2* row = tile + yy * ROW;
+        // transmission of this row, requested before the inverse transforms
+        // so the load latency hides behind them
+        float4 trow[E];
+        {
+            const float4* Trow = reinterpret_cast<const float4*>(T + (size_t)y * N);
+#pragma unroll
+            for (int i = 0; i < E; ++i) trow[i] = Trow[lt + LPT * i];
+        }
         float2 e[E], o[E];
         if constexpr (FIRST) {
             // plane wave e^{2 pi i (kx x + ky y)/N} at x = 2m, 2m+1 (exact integer phase)
@@ -112,18 +141,24 @@ __global__ __launch_bounds__(WG) void k_pass_a(float2* __restrict__ W, const flo
                 e[i] = row[F::pad(lt + LPT * i)];
                 o[i] = cmulc(e[i], btw[i]);
             }
-            F::template run<+1>(e, row, tw, lt);
-            F::template run<+1>(o, row, tw, lt);
+            if constexpr (PRISM_PASSA_ILP) {
+                F::template run2<+1>(e, o, row, xodd + (wave * G + g) * F::LDS, tw, lt);
+            } else {
+                F::template run<+1>(e, row, tw, lt);
+                F::template run<+1>(o, row, tw, lt);
+            }
         }
-        const float4* Trow = reinterpret_cast<const float4*>(T + (size_t)y * N);
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            float4 t = Trow[lt + LPT * i];
-            e[i] = cmul(e[i], make_float2(t.x, t.y));
-            o[i] = cmul(o[i], make_float2(t.z, t.w));
+            e[i] = cmul(e[i], make_float2(trow[i].x, trow[i].y));
+            o[i] = cmul(o[i], make_float2(trow[i].z, trow[i].w));
         }
-        F::template run<-1>(e, row, tw, lt);
-        F::template run<-1>(o, row, tw, lt);
+        if constexpr (PRISM_PASSA_ILP) {
+            F::template run2<-1>(e, o, row, xodd + (wave * G + g) * F::LDS, tw, lt);
+        } else {
+            F::template run<-1>(e, row, tw, lt);
+            F::template run<-1>(o, row, tw, lt);
+        }
         wave_sync();
 #pragma unroll
         for (int i = 0; i < E; ++i) row[F::pad(lt + LPT * i)] = cadd(e[i], cmul(btw[i], o[i]));
@@ -131,7 +166,7 @@ __global__ __launch_bounds__(WG) void k_pass_a(float2* __restrict__ W, const flo
     __syncthreads();
     for (int idx = tid; idx < L * TR; idx += WG) {
         int yy = idx % TR, j = idx / TR;
-        Wi[(size_t)j * N + y0 + yy] = tile[yy * ROW + F::pad(j)];
+        Wi[(size_t)j * CS + y0 + yy] = tile[yy * ROW + F::pad(j)];
     }
 }
 
@@ -162,13 +197,13 @@ hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb
 
 // ------------------------------------------------------------------ pass B --
 template <int N, int MODE>
-__global__ __launch_bounds__(WG) void k_pass_b(float2* __restrict__ W, PropTables tb, float2* __restrict__ out_half,
-                                               float* __restrict__ inten, const int* __restrict__ ky_max,
-                                               const double2* __restrict__ probe_xy, double inv_L, float amp,
-                                               int n_items) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_WPE))) void k_pass_b(
+    float2* __restrict__ W, PropTables tb, float2* __restrict__ out_half, float* __restrict__ inten,
+    const int* __restrict__ ky_max, const double2* __restrict__ probe_xy, double inv_L, float amp, int n_items) {
     using F = Fft<N / 2>;
     constexpr int L = N / 2, E = F::E, LPT = F::LPT, G = 64 / LPT, CPB = 4 * G;
-    __shared__ float2 xch[CPB * F::LDS];
+    constexpr int NB = PRISM_PASSB_ILP ? 2 : 1;
+    __shared__ float2 xch[NB * CPB * F::LDS];
 
     const int item = blockIdx.x % n_items;
     const int cb = blockIdx.x / n_items;
@@ -177,6 +212,7 @@ __global__ __launch_bounds__(WG) void k_pass_b(float2* __restrict__ W, PropTable
     const int j = cb * CPB + wave * G + g;
     if (j >= L) return;                          // whole transform groups exit together
     float2* lds = xch + (wave * G + g) * F::LDS;
+    float2* lds2 = xch + ((NB - 1) * CPB + wave * G + g) * F::LDS;
     const int kxj = j < N / 4 ? j : j - N / 2;
 
     typename F::Twiddles tw;
@@ -185,7 +221,7 @@ __global__ __launch_bounds__(WG) void k_pass_b(float2* __restrict__ W, PropTable
 #pragma unroll
     for (int i = 0; i < E; ++i) btw[i] = tb.band_tw[lt + LPT * i];
 
-    float2* col = W + ((size_t)item * L + j) * N;
+    float2* col = W + ((size_t)item * L + j) * wave_col_stride(N);
     float4* col4 = reinterpret_cast<float4*>(col);
     float2 e[E], o[E];
 
@@ -209,8 +245,12 @@ __global__ __launch_bounds__(WG) void k_pass_b(float2* __restrict__ W, PropTable
             e[i] = c;
             o[i] = cmulc(c, btw[i]);
         }
-        F::template run<+1>(e, lds, tw, lt);
-        F::template run<+1>(o, lds, tw, lt);
+        if constexpr (PRISM_PASSB_ILP) {
+            F::template run2<+1>(e, o, lds, lds2, tw, lt);
+        } else {
+            F::template run<+1>(e, lds, tw, lt);
+            F::template run<+1>(o, lds, tw, lt);
+        }
 #pragma unroll
         for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
         return;
@@ -222,8 +262,12 @@ __global__ __launch_bounds__(WG) void k_pass_b(float2* __restrict__ W, PropTable
         e[i] = make_float2(v.x, v.y);
         o[i] = make_float2(v.z, v.w);
     }
-    F::template run<-1>(e, lds, tw, lt);
-    F::template run<-1>(o, lds, tw, lt);
+    if constexpr (PRISM_PASSB_ILP) {
+        F::template run2<-1>(e, o, lds, lds2, tw, lt);
+    } else {
+        F::template run<-1>(e, lds, tw, lt);
+        F::template run<-1>(o, lds, tw, lt);
+    }
     const float2 pj = tb.prop[j];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -249,8 +293,12 @@ __global__ __launch_bounds__(WG) void k_pass_b(float2* __restrict__ W, PropTable
     }
 #pragma unroll
     for (int i = 0; i < E; ++i) o[i] = cmulc(e[i], btw[i]);
-    F::template run<+1>(e, lds, tw, lt);
-    F::template run<+1>(o, lds, tw, lt);
+    if constexpr (PRISM_PASSB_ILP) {
+        F::template run2<+1>(e, o, lds, lds2, tw, lt);
+    } else {
+        F::template run<+1>(e, lds, tw, lt);
+        F::template run<+1>(o, lds, tw, lt);
+    }
 #pragma unroll
     for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
 }
@@ -308,11 +356,12 @@ __global__ __launch_bounds__(WG) void k_smatrix_final(const float2* __restrict__
 
     const int item = blockIdx.x % n_items;
     const int y0 = (blockIdx.x / n_items) * TRV;
-    const float2* Hi = half + (size_t)item * L * N;
+    constexpr int CS = wave_col_stride(N);
+    const float2* Hi = half + (size_t)item * L * CS;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < L * TRV; idx += WG) {
         int yy = idx % TRV, j = idx / TRV;
-        tile[yy * ROW + F::pad(j)] = Hi[(size_t)j * N + y0 + yy];
+        tile[yy * ROW + F::pad(j)] = Hi[(size_t)j * CS + y0 + yy];
     }
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
