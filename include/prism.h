@@ -84,14 +84,16 @@ typedef struct prism_smatrix_desc {
     double E0;               /* beam energy (eV) */
     double alpha_max;        /* largest beam angle = probe semi-angle (rad) */
     int32_t f;               /* interpolation factor: every f-th plane wave per axis */
+    int32_t beam_batch;      /* input: beams propagated per launch, 0 = all; bounds the workspace */
     int32_t n_beams;         /* |B_f| */
+    int32_t ns;              /* S-matrix side n/2 */
+    int32_t m_win;           /* probe window side ns/f */
+    int32_t pad;
     double lambda;           /* relativistic wavelength (A) */
     double sigma;            /* interaction constant (rad / (V*A)) */
     double alpha_aa;         /* anti-aliasing angle lambda*n/(4L) (rad) */
-    int32_t ns;              /* S-matrix side n/2 */
-    int32_t m_win;           /* probe window side ns/f */
     size_t smatrix_bytes;    /* n_beams * ns * ns * 8 */
-    size_t build_ws_bytes;   /* workspace of prism_build_smatrix */
+    size_t build_ws_bytes;   /* workspace of prism_build_smatrix for min(beam_batch, n_beams) beams per launch */
 } prism_smatrix_desc;
 
 /* Probe-synthesis plan (host side of a plan whose tables live in device memory). */
@@ -135,8 +137,9 @@ int prism_project_potential(const prism_atom* atoms, int64_t n_atoms,
 /* Fill the derived fields of *d: lambda, sigma, alpha_aa, beams B_f = every
  * f-th Fourier index (kx, ky) per axis with lambda*sqrt(kx^2+ky^2)/L <= alpha_max,
  * ns = n/2, m_win = ns/f, and the byte sizes.
- * Errors: PRISM_E_INVAL (E0 <= 0, alpha_max <= 0, f < 1), PRISM_E_UNSUPPORTED
- * (alpha_max >= alpha_aa, f not dividing ns, m_win outside [16, 128]). */
+ * Errors: PRISM_E_INVAL (E0 <= 0, alpha_max <= 0, f < 1, beam_batch < 0),
+ * PRISM_E_UNSUPPORTED (alpha_max >= alpha_aa, f not dividing ns, m_win outside
+ * [16, 512]). */
 int prism_smatrix_plan(prism_smatrix_desc* d);
 
 /* Copy the beam list (kx, ky pairs, host int32 [cap][2]) in the order of the

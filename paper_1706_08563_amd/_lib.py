@@ -37,8 +37,9 @@ class prism_grid(ctypes.Structure):
 
 class prism_smatrix_desc(ctypes.Structure):
     _fields_ = [("grid", prism_grid), ("E0", c_double), ("alpha_max", c_double), ("f", c_int32),
-                ("n_beams", c_int32), ("lambda_", c_double), ("sigma", c_double), ("alpha_aa", c_double),
-                ("ns", c_int32), ("m_win", c_int32), ("smatrix_bytes", c_size_t), ("build_ws_bytes", c_size_t)]
+                ("beam_batch", c_int32), ("n_beams", c_int32), ("ns", c_int32), ("m_win", c_int32),
+                ("pad", c_int32), ("lambda_", c_double), ("sigma", c_double), ("alpha_aa", c_double),
+                ("smatrix_bytes", c_size_t), ("build_ws_bytes", c_size_t)]
 
 
 class prism_probe_plan(ctypes.Structure):

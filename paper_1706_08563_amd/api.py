@@ -43,12 +43,14 @@ def prism_grid_init(cell, dz: float, n: int) -> prism_grid:
 
 
 # ------------------------------------------------------------ S-matrix --
-def prism_smatrix_plan(grid: prism_grid, E0: float, alpha_max: float, f: int) -> prism_smatrix_desc:
+def prism_smatrix_plan(grid: prism_grid, E0: float, alpha_max: float, f: int,
+                       beam_batch: int = 0) -> prism_smatrix_desc:
     d = prism_smatrix_desc()
     d.grid = grid
     d.E0 = float(E0)
     d.alpha_max = float(alpha_max)
     d.f = int(f)
+    d.beam_batch = int(beam_batch)
     check(lib.prism_smatrix_plan(ctypes.byref(d)))
     return d
 

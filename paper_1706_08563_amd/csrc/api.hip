@@ -297,6 +297,10 @@ int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, 
     return PRISM_OK;
 }
 
+int batch_of(const prism_smatrix_desc* d) {
+    return (d->beam_batch > 0 && d->beam_batch < d->n_beams) ? d->beam_batch : d->n_beams;
+}
+
 int check_desc(const prism_smatrix_desc* d) {
     if (!d) return fail(PRISM_E_INVAL, "descriptor is NULL");
     prism_smatrix_desc c = *d;
@@ -424,8 +428,8 @@ int prism_smatrix_plan(prism_smatrix_desc* d) {
     if (!d) return fail(PRISM_E_INVAL, "descriptor is NULL");
     int rc = check_grid(&d->grid);
     if (rc) return rc;
-    if (!(d->E0 > 0) || !(d->alpha_max > 0) || d->f < 1)
-        return fail(PRISM_E_INVAL, "smatrix: E0, alpha_max must be positive and f >= 1");
+    if (!(d->E0 > 0) || !(d->alpha_max > 0) || d->f < 1 || d->beam_batch < 0)
+        return fail(PRISM_E_INVAL, "smatrix: E0, alpha_max must be positive, f >= 1, beam_batch >= 0");
     const int n = d->grid.n;
     const double L = d->grid.cell[0];
     d->lambda = wavelength_A(d->E0);
@@ -437,15 +441,15 @@ int prism_smatrix_plan(prism_smatrix_desc* d) {
     d->ns = n / 2;
     if (d->ns % d->f != 0) return fail(PRISM_E_UNSUPPORTED, "smatrix: f = %d must divide n/2 = %d", d->f, d->ns);
     d->m_win = d->ns / d->f;
-    if (d->m_win < 16 || d->m_win > 128)
-        return fail(PRISM_E_UNSUPPORTED, "smatrix: window side n/(2f) = %d outside [16, 128]", d->m_win);
+    if (d->m_win < 16 || d->m_win > 512)
+        return fail(PRISM_E_UNSUPPORTED, "smatrix: window side n/(2f) = %d outside [16, 512]", d->m_win);
     d->n_beams = (int32_t)beam_list(n, L, d->lambda, d->alpha_max, d->f).size();
     d->smatrix_bytes = (size_t)d->n_beams * d->ns * d->ns * sizeof(float2);
     Carve c(nullptr);
     carve_prop(c, n);
     c.take<int2>(d->n_beams);
     c.take<float2>((size_t)d->grid.n_slices * n * n);
-    c.take<float2>((size_t)d->n_beams * (n / 2) * wave_col_stride(n));
+    c.take<float2>((size_t)batch_of(d) * (n / 2) * wave_col_stride(n));
     d->build_ws_bytes = c.off + 256;
     return PRISM_OK;
 }
@@ -469,14 +473,14 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     if (!V || !S) return fail(PRISM_E_INVAL, "build: NULL V or S");
     if (!ws || ws_bytes < d->build_ws_bytes)
         return fail(PRISM_E_WORKSPACE, "build: workspace %zu < %zu bytes", ws_bytes, d->build_ws_bytes);
-    const int n = d->grid.n, B = d->n_beams, nsl = d->grid.n_slices;
+    const int n = d->grid.n, B = d->n_beams, nsl = d->grid.n_slices, NB = batch_of(d);
     const double L = d->grid.cell[0];
     hipStream_t st = as_stream(stream);
     Carve c(ws);
     PropDev pd = carve_prop(c, n);
     int2* d_beams = c.take<int2>(B);
     float2* T = c.take<float2>((size_t)nsl * n * n);
-    float2* W = c.take<float2>((size_t)B * (n / 2) * wave_col_stride(n));
+    float2* W = c.take<float2>((size_t)NB * (n / 2) * wave_col_stride(n));
     PropHost ph = prop_tables(n, L, d->lambda, d->grid.dz);
     std::vector<char> blob;
     stage(blob, ws, pd.tw_half, ph.tw_half);
@@ -488,14 +492,20 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     if (rc) return rc;
     const PropTables tb = pd.tables();
     HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(V, T, (int64_t)nsl * n * n, (float)d->sigma, st); }));
-    for (int s = 0; s < nsl; ++s) {
-        HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, W, T + (size_t)s * n * n, tb, d_beams, s == 0, B, st); }));
-        HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
-            return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, W, tb, nullptr, nullptr, nullptr, nullptr,
-                                 0.0, 0.f, B, st);
-        }));
+    float2* Sout = static_cast<float2*>(S);
+    for (int b0 = 0; b0 < B; b0 += NB) {
+        const int nb = std::min(NB, B - b0);
+        const int2* bb = d_beams + b0;
+        for (int s = 0; s < nsl; ++s) {
+            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, W, T + (size_t)s * n * n, tb, bb, s == 0, nb, st); }));
+            HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
+                return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, W, tb, nullptr, nullptr, nullptr,
+                                     nullptr, 0.0, 0.f, nb, st);
+            }));
+        }
+        float2* Sb = Sout + (size_t)b0 * (n / 2) * (n / 2);
+        HIP_TRY(timed(PRISM_K_FINAL, st, [&] { return launch_smatrix_final(n, W, Sb, pd.tw_half, nb, st); }));
     }
-    HIP_TRY(timed(PRISM_K_FINAL, st, [&] { return launch_smatrix_final(n, W, static_cast<float2*>(S), pd.tw_half, B, st); }));
     return PRISM_OK;
 }
 
@@ -533,6 +543,7 @@ int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, i
     Carve w(nullptr);
     w.take<float2>(P * d->n_beams);
     w.take<float2>(P * d->m_win * d->m_win);
+    if (d->m_win > 128) w.take<float>(P * d->m_win * d->m_win);
     p.ws_bytes = w.off + 256;
     *plan = p;
     return PRISM_OK;
@@ -588,6 +599,7 @@ int prism_probe_outputs(const prism_smatrix_desc* d, const void* S, const prism_
     Carve c(ws);
     float2* C = c.take<float2>((size_t)P * B);
     float2* win = c.take<float2>((size_t)P * M * M);
+    float* inten = M > 128 ? c.take<float>((size_t)P * M * M) : nullptr;
     hipStream_t st = as_stream(stream);
     HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
         return launch_coefficients(C, xy, beams, P, B, 1.0 / d->grid.cell[0], (float)(1.0 / std::sqrt((double)B)), st);
@@ -597,7 +609,7 @@ int prism_probe_outputs(const prism_smatrix_desc* d, const void* S, const prism_
                                plan->n_tiles, plan->max_per_tile, B, d->ns, M, st);
     }));
     HIP_TRY(timed(PRISM_K_WINDOW, st, [&] {
-        return launch_window_detect(M, win, out, perm, bstart, tw_m, P, plan->n_bins, st);
+        return launch_window_detect(M, win, inten, out, perm, bstart, tw_m, P, plan->n_bins, st);
     }));
     return PRISM_OK;
 }

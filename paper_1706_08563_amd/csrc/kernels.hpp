@@ -60,8 +60,10 @@ hipError_t launch_contract(int precision, const float2* C, const float2* S, floa
                            const int* tile_start, const int* tile_probes, const int2* corner,
                            int n_tiles, int max_per_tile, int n_beams, int ns, int m, hipStream_t st);
 
-// out[p][bin] = sum over the bin's pixels of |FFT_m(win[p])|^2 / m^4.
-hipError_t launch_window_detect(int m, const float2* win, float* out, const int* perm, const int* bin_start,
+// out[p][bin] = sum over the bin's pixels of |FFT_m(win[p])|^2 / m^4.  For
+// m > 128 the window is transformed in place and `inten` ([p][m*m] floats)
+// holds the intensities; for m <= 128 both stay untouched.
+hipError_t launch_window_detect(int m, float2* win, float* inten, float* out, const int* perm, const int* bin_start,
                                 const float2* tw_m, int n_probes, int n_bins, hipStream_t st);
 
 // out[p][bin] = sum over bin pixels of inten[p][pix] (deterministic order).

@@ -337,7 +337,25 @@ __global__ __launch_bounds__(WG) void k_window_detect(const float2* __restrict__
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane / LPT, lt = lane % LPT;
     const float2* w = win + (size_t)p * M * M;
-    for (int idx = tid; idx < M * M; idx += WG) buf[(idx / M) * ROW + F::pad(idx % M)] = w[idx];
+    {
+        // batches of loads in flight before their LDS stores
+        constexpr int NLD = (M * M + WG - 1) / WG, BATCH = NLD < 16 ? NLD : 16;
+        static_assert(NLD % BATCH == 0, "load batches must divide the window");
+#pragma unroll 1
+        for (int k0 = 0; k0 < NLD; k0 += BATCH) {
+            float2 ld[BATCH];
+#pragma unroll
+            for (int k = 0; k < BATCH; ++k) {
+                const int idx = tid + (k0 + k) * WG;
+                if (idx < M * M) ld[k] = w[idx];
+            }
+#pragma unroll
+            for (int k = 0; k < BATCH; ++k) {
+                const int idx = tid + (k0 + k) * WG;
+                if (idx < M * M) buf[(idx / M) * ROW + F::pad(idx % M)] = ld[k];
+            }
+        }
+    }
     __syncthreads();
     typename F::Twiddles tw;
     tw.load(tw_m, lt);
@@ -385,13 +403,96 @@ static hipError_t window_m(const float2* win, float* out, const int* perm, const
     return hipGetLastError();
 }
 
-hipError_t launch_window_detect(int m, const float2* win, float* out, const int* perm, const int* bin_start,
+// ---------------------------------------- large windows (M = 256, 512) --
+// A window no longer fits in LDS: rows are transformed in place in HBM, then
+// 16-column strips are staged through LDS for the column transforms, which
+// write |Psi|^2 / M^4 to an intensity buffer binned by k_bin_reduce.
+template <int M>
+__global__ __launch_bounds__(WG) void k_window_rows(float2* __restrict__ win, const float2* __restrict__ tw_m,
+                                                    int64_t n_rows) {
+    using F = Fft<M>;
+    constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT;
+    __shared__ float2 xch[4 * G * F::LDS];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane / LPT, lt = lane % LPT;
+    const int64_t r = (int64_t)blockIdx.x * 4 * G + wave * G + g;
+    if (r >= n_rows) return;
+    typename F::Twiddles tw;
+    tw.load(tw_m, lt);
+    float2* row = win + r * M;
+    float2 v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = row[lt + LPT * i];
+    F::template run<-1>(v, xch + (wave * G + g) * F::LDS, tw, lt);
+#pragma unroll
+    for (int i = 0; i < E; ++i) row[lt + LPT * i] = v[i];
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_window_cols(const float2* __restrict__ win, float* __restrict__ inten,
+                                                    const float2* __restrict__ tw_m) {
+    using F = Fft<M>;
+    constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, CW = 16, ROWS = CW + 1;
+    __shared__ float2 strip[M * ROWS];
+    const int p = blockIdx.y, u0 = blockIdx.x * CW;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane / LPT, lt = lane % LPT;
+    const float2* w = win + (size_t)p * M * M;
+    {
+        constexpr int NLD = M * CW / WG;
+        float2 ld[NLD];
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, v = idx / CW, c = idx % CW;
+            ld[k] = w[(size_t)v * M + u0 + c];
+        }
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, v = idx / CW, c = idx % CW;
+            strip[v * ROWS + c] = ld[k];
+        }
+    }
+    __syncthreads();
+    typename F::Twiddles tw;
+    tw.load(tw_m, lt);
+    const float scale = 1.0f / ((float)M * (float)M * (float)M * (float)M);
+    float* I = inten + (size_t)p * M * M;
+    for (int c0 = wave * G; c0 < CW; c0 += 4 * G) {
+        const int c = c0 + g;
+        float2* col = strip + c;
+        float2 v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = col[(lt + LPT * i) * ROWS];
+        F::template run_col<-1>(v, col, ROWS, tw, lt);
+#pragma unroll
+        for (int i = 0; i < E; ++i) I[(size_t)(lt + LPT * i) * M + u0 + c] = cnorm(v[i]) * scale;
+    }
+}
+
+template <int M>
+static hipError_t window_large(float2* win, float* inten, float* out, const int* perm, const int* bin_start,
+                               const float2* tw_m, int n_probes, int n_bins, hipStream_t st) {
+    constexpr int G = 64 / Fft<M>::LPT;
+    const int64_t rows = (int64_t)n_probes * M;
+    hipLaunchKernelGGL((k_window_rows<M>), dim3((unsigned)((rows + 4 * G - 1) / (4 * G))), dim3(WG), 0, st, win,
+                       tw_m, rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_window_cols<M>), dim3(M / 16, (unsigned)n_probes), dim3(WG), 0, st, win, inten, tw_m);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_bin_reduce(inten, (int64_t)M * M, out, perm, bin_start, n_probes, n_bins, st);
+}
+
+hipError_t launch_window_detect(int m, float2* win, float* inten, float* out, const int* perm, const int* bin_start,
                                 const float2* tw_m, int n_probes, int n_bins, hipStream_t st) {
     switch (m) {
         case 16: return window_m<16>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
         case 32: return window_m<32>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
         case 64: return window_m<64>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
         case 128: return window_m<128>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
+        case 256: return window_large<256>(win, inten, out, perm, bin_start, tw_m, n_probes, n_bins, st);
+        case 512: return window_large<512>(win, inten, out, perm, bin_start, tw_m, n_probes, n_bins, st);
     }
     return hipErrorInvalidValue;
 }

@@ -91,9 +91,19 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
     const int tid = threadIdx.x;
 
     if constexpr (!FIRST) {
-        for (int idx = tid; idx < L * TR; idx += WG) {
-            int yy = idx % TR, j = idx / TR;
-            tile[yy * ROW + F::pad(j)] = Wi[(size_t)j * CS + y0 + yy];
+        // all loads of the tile in flight before the first LDS store
+        static_assert((L * TR) % WG == 0, "tile must split evenly over the workgroup");
+        constexpr int NLD = L * TR / WG;
+        float2 ld[NLD];
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, yy = idx % TR, j = idx / TR;
+            ld[k] = Wi[(size_t)j * CS + y0 + yy];
+        }
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, yy = idx % TR, j = idx / TR;
+            tile[yy * ROW + F::pad(j)] = ld[k];
         }
         __syncthreads();
     }
@@ -164,8 +174,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
         for (int i = 0; i < E; ++i) row[F::pad(lt + LPT * i)] = cadd(e[i], cmul(btw[i], o[i]));
     }
     __syncthreads();
-    for (int idx = tid; idx < L * TR; idx += WG) {
-        int yy = idx % TR, j = idx / TR;
+#pragma unroll
+    for (int k = 0; k < L * TR / WG; ++k) {
+        const int idx = tid + k * WG, yy = idx % TR, j = idx / TR;
         Wi[(size_t)j * CS + y0 + yy] = tile[yy * ROW + F::pad(j)];
     }
 }
@@ -359,9 +370,19 @@ __global__ __launch_bounds__(WG) void k_smatrix_final(const float2* __restrict__
     constexpr int CS = wave_col_stride(N);
     const float2* Hi = half + (size_t)item * L * CS;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < L * TRV; idx += WG) {
-        int yy = idx % TRV, j = idx / TRV;
-        tile[yy * ROW + F::pad(j)] = Hi[(size_t)j * CS + y0 + yy];
+    {
+        constexpr int NLD = (L * TRV + WG - 1) / WG;
+        float2 ld[NLD];
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, yy = idx % TRV, j = idx / TRV;
+            if (idx < L * TRV) ld[k] = Hi[(size_t)j * CS + y0 + yy];
+        }
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, yy = idx % TRV, j = idx / TRV;
+            if (idx < L * TRV) tile[yy * ROW + F::pad(j)] = ld[k];
+        }
     }
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;

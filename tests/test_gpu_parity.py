@@ -220,3 +220,67 @@ def test_config0_prism_and_multislice_full(P):
     _check_D(out3.cpu().numpy().astype(np.float64), ref, "config0 prism split-bf16")
     mref = O.multislice_outputs(Vref, L, w.dz, d.lambda_, d.sigma, w.alpha_max, xy[::17])
     _check_D(ms.cpu().numpy().astype(np.float64), mref, "config0 multislice")
+
+
+# ------------------------------------------------- batching, large sizes --
+def test_smatrix_beam_batches_match_oracle(P):
+    """Beams propagated in ragged batches (7 per launch) give the oracle's layers."""
+    import torch
+    say("smatrix beam_batch=7 n=128 f=2")
+    n, L, S, f = 128, 16.0, 2, 2
+    rng = np.random.default_rng(21)
+    Vr = _random_potential(rng, S, n)
+    g = P.prism_grid_init((L, L, 2.0 * S), 2.0, n)
+    d = P.prism_smatrix_plan(g, 80e3, 0.02, f, beam_batch=7)
+    assert d.n_beams % 7 != 0
+    Sg = P.prism_build_smatrix(d, torch.tensor(Vr, dtype=torch.float32, device="cuda"))
+    _sync()
+    beams = O.beam_set(n, L, d.lambda_, 0.02, f)
+    ref = O.build_smatrix(Vr.astype(np.float32).astype(np.float64), L, 2.0, d.lambda_, d.sigma, beams)
+    got = Sg.cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= TOL
+
+
+def test_smatrix_2048_sampled_layers(P):
+    """2048^2 grid, 2 slices, f = 8 (1245 beams): sampled layers against the oracle."""
+    import torch
+    say("smatrix n=2048 S=2 f=8 sampled layers")
+    n, L, S, f = 2048, 200.0, 2, 8
+    rng = np.random.default_rng(22)
+    Vr = _random_potential(rng, S, n)
+    g = P.prism_grid_init((L, L, 2.0 * S), 2.0, n)
+    d = P.prism_smatrix_plan(g, 200e3, 0.02, f)
+    Sg = P.prism_build_smatrix(d, torch.tensor(Vr, dtype=torch.float32, device="cuda"))
+    _sync()
+    beams = P.prism_beam_list(d)
+    t = O.transmission(Vr.astype(np.float32).astype(np.float64), d.sigma)
+    Pp = O.propagator(n, L, d.lambda_, 2.0)
+    for b in (0, len(beams) // 2, len(beams) - 1):
+        ref = O.smatrix_layer(t, Pp, int(beams[b, 0]), int(beams[b, 1]))
+        got = Sg[b].cpu().numpy().astype(np.complex128)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        say(f"  beam {b} ({beams[b, 0]}, {beams[b, 1]}): {err:.3e}")
+        assert err <= TOL
+
+
+@pytest.mark.parametrize("n,L,f,a,prec", [(512, 40.0, 1, 0.008, 0), (1024, 100.0, 2, 0.006, 1),
+                                          (2048, 200.0, 2, 0.0025, 1)])
+def test_prism_synthesis_large_windows(P, n, L, f, a, prec):
+    """Windows of 256 and 512 pixels (two-pass transforms) on random S-matrices
+    (small apertures keep the host-side oracle operands to a few hundred beams)."""
+    import torch
+    say(f"prism synthesis large window n={n} f={f} precision={prec}")
+    g = P.prism_grid_init((L, L, 2.0), 2.0, n)
+    d = P.prism_smatrix_plan(g, 200e3, a, f)
+    assert d.m_win in (256, 512)
+    rng = np.random.default_rng(31 + n)
+    S = W.random_complex((d.n_beams, d.ns, d.ns), rng)
+    xy = np.concatenate([W.random_positions((L, L), 5, rng), [[0.0, 0.0], [L * 0.999, 1.0]]])
+    plan = P.prism_probe_plan_upload(d, xy)
+    out = P.prism_probe_outputs(d, torch.tensor(S, device="cuda"), plan, prec)
+    _sync()
+    beams = P.prism_beam_list(d).astype(np.int64)
+    ref = O.prism_outputs(S.astype(np.complex128), beams, L, n, d.lambda_, f, xy)
+    err = O.rel_err(out.cpu().numpy().astype(np.float64), ref)
+    say(f"  M={d.m_win} beams={d.n_beams}: rel_all={err:.3e}")
+    assert err <= TOL
