@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-beams", type=int, default=3)
     ap.add_argument("--cpu-probes", type=int, default=12)
+    ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson stream of mixed requests)")
+    ap.add_argument("--requests", type=int, default=40)
+    ap.add_argument("--load", type=float, default=0.8, help="offered load against the modelled capacity")
+    ap.add_argument("--grids", default="256,512,1024,2048")
     return ap.parse_args()
 
 
@@ -85,12 +89,96 @@ def cpu_baseline(w, d, n_beams, n_probes, args):
             "beams_per_s": 1.0 / t_beam}
 
 
+def run_serving(args):
+    """Continuous-batching serving of a Poisson stream of mixed PRISM requests."""
+    import numpy as np
+    import torch
+
+    import paper_1706_08563_amd as P
+    from paper_1706_08563_amd import serve as SV
+    import workloads as W
+
+    prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
+    grids = tuple(int(x) for x in args.grids.split(","))
+    params = W.serving_stream(args.requests, 1.0, grids=grids)
+    # offered load: rate = load / modelled mean service time, the model being
+    # the 1024^2 build cost per beam-slice scaled by n^2 log n, plus synthesis
+    per_bs = 4.6e-6
+    cost = []
+    for p in params:
+        r = SV.Request(**p)
+        g = P.prism_grid_init(r.cell, 2.0, r.n)
+        d = P.prism_smatrix_plan(g, r.E0, r.alpha_max, r.f)
+        scale = (r.n / 1024.0) ** 2 * math.log2(r.n) / 10.0
+        cost.append(per_bs * d.n_beams * r.n_slices * scale + 1.5e-6 * r.n_probes * d.n_beams / 1245.0)
+    rate = args.load / float(np.mean(cost))
+    params = W.serving_stream(args.requests, rate, grids=grids)
+    reqs = []
+    for p in params:
+        r = SV.Request(**p)
+        r.sample = W.serving_sample(r.cell, r.seed)
+        reqs.append(r)
+    free, total = torch.cuda.mem_get_info()
+    cap = int(0.8 * free)
+    log(f"serving {len(reqs)} requests at {rate:.3f}/s, budget {cap / 1e9:.1f} GB")
+    ex = SV.GpuExecutor(prec)
+    sched = SV.Scheduler(cap, max_building=4, max_jobs=24)
+    t0 = time.perf_counter()
+    SV.serve(reqs, ex, sched, on_done=lambda r: log(f"  done {r.rid} n={r.n} f={r.f} S={r.n_slices} "
+                                                    f"P={r.n_probes} latency {r.latency:.2f} s"))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    summ = SV.summarize(sched, wall)
+    # alone vs in the mix, for the three smallest requests
+    small = sorted(sched.done, key=lambda r: r.n * r.n * r.n_slices)[:3]
+    diffs = []
+    for r in small:
+        a = SV.Request(r.rid, 0.0, r.n, r.f, r.n_slices, r.scan, r.seed, sample=W.serving_sample(r.cell, r.seed))
+        SV.serve([a], SV.GpuExecutor(prec), SV.Scheduler(cap, max_building=1, max_jobs=1))
+        diffs.append(float(np.max(np.abs(a.result - r.result))))
+    # sequential plain multislice on the same GPU, timed per (n, slices) class
+    # on 8 probes and extrapolated to every request's scan
+    ms_time = 0.0
+    classes = {}
+    for r in sched.done:
+        classes.setdefault((r.n, r.n_slices), []).append(r)
+    for (n, ns), rs in classes.items():
+        r = rs[0]
+        g = P.prism_grid_init(r.cell, 2.0, n)
+        pos, sp, species = r.sample() if callable(r.sample) else W.serving_sample(r.cell, r.seed)()
+        V = P.prism_project_potential(pos, sp, species, g)
+        xy = W.scan_positions(r.cell, 8, 1)
+        ws = torch.empty(P.multislice_workspace(g, 8, 8), dtype=torch.uint8, device="cuda")
+        P.multislice_outputs(g, r.E0, r.alpha_max, V, xy, batch=8, ws=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P.multislice_outputs(g, r.E0, r.alpha_max, V, xy, batch=8, ws=ws)
+        torch.cuda.synchronize()
+        per_probe = (time.perf_counter() - t1) / 8
+        ms_time += per_probe * sum(x.n_probes for x in rs)
+    res = {"metric": "serving: aggregate probe positions/s, p50/p99 latency (mixed PRISM requests)",
+           "value": summ["probes_per_s"], "unit": "probe positions/s", "n_gpus": 1,
+           "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+           "requests": summ["requests"], "rejected": summ["rejected"], "probes": summ["probes"],
+           "wall_s": wall, "arrival_rate_per_s": rate, "offered_load": args.load,
+           "hbm_budget_GB": cap / 1e9, "peak_reserved_GB": summ["peak_hbm_reserved"] / 1e9,
+           "precision": args.precision, "grids": list(grids),
+           "alone_vs_mix_max_abs_diff": max(diffs) if diffs else None,
+           "sequential_multislice_s_extrapolated": ms_time,
+           "speedup_vs_sequential_multislice": ms_time / wall if wall > 0 else None,
+           "data": "synthetic"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "detail": "multi-GPU sharding is described in the design notes, not implemented"}))
         sys.exit(2)
+    if args.serve:
+        run_serving(args)
+        return
 
     import numpy as np
     import torch

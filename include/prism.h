@@ -182,6 +182,29 @@ int prism_probe_outputs(const prism_smatrix_desc* d, const void* S,
                         int32_t precision, float* out,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* One request's probe synthesis inside a batched call (all pointers borrowed
+ * for the call; device pointers as in prism_probe_outputs). */
+typedef struct prism_probe_job {
+    const prism_smatrix_desc* desc;   /* host */
+    const void* S;                    /* device complex64 [n_beams][ns][ns] */
+    const prism_probe_plan* plan;     /* host */
+    const void* plan_dev;             /* device plan tables */
+    float* out;                       /* device float32 [n_probes][n_bins] */
+} prism_probe_job;
+
+/* Workspace bytes of prism_probe_outputs_batched for these jobs. */
+int prism_probe_batch_workspace(const prism_probe_job* jobs, int32_t n_jobs, size_t* bytes);
+
+/* Probe outputs of several independent jobs (different S-matrices, grids,
+ * interpolation factors and probe sets) in one pass on one stream: the
+ * windowed contractions of all jobs share launches, as do the window
+ * transforms of jobs with the same window side.  Each job's result is the
+ * one prism_probe_outputs gives for it alone (same kernels, same order of
+ * operations).  Fully asynchronous.
+ * Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
+int prism_probe_outputs_batched(const prism_probe_job* jobs, int32_t n_jobs, int32_t precision,
+                                void* ws, size_t ws_bytes, void* stream);
+
 /* ---- multislice probe outputs (Fig. 1c-e) --------------------------------- */
 
 /* Workspace bytes for multislice_outputs over n_probes probes processed

@@ -8,11 +8,12 @@ the library has not been built.
 from ._lib import (  # noqa: F401
     PRISM_OK, PRISM_E_INVAL, PRISM_E_UNSUPPORTED, PRISM_E_NOMEM, PRISM_E_DEVICE, PRISM_E_WORKSPACE,
     PRISM_FP32, PRISM_SPLIT_BF16X3, PRISM_BF16, PrismError, EXPORTED, LIB_PATH,
-    prism_atom, prism_species, prism_grid, prism_smatrix_desc, prism_probe_plan, TIMING_CLASSES,
+    prism_atom, prism_species, prism_grid, prism_smatrix_desc, prism_probe_plan, prism_probe_job, TIMING_CLASSES,
 )
 from .api import (  # noqa: F401
     lib, prism_grid_init, prism_smatrix_plan, prism_beam_list, prism_detector_bin_map,
     prism_project_potential, prism_build_smatrix, prism_probe_plan_init, prism_probe_plan_upload,
     prism_probe_outputs, multislice_outputs, multislice_workspace, ProbePlan,
     prism_timing_enable, prism_timing_reset, prism_timing_read,
+    prism_probe_batch_workspace, prism_probe_outputs_batched,
 )

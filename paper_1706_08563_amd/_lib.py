@@ -48,6 +48,11 @@ class prism_probe_plan(ctypes.Structure):
                 ("plan_bytes", c_size_t), ("ws_bytes", c_size_t), ("off", c_size_t * 8)]
 
 
+class prism_probe_job(ctypes.Structure):
+    _fields_ = [("desc", POINTER(prism_smatrix_desc)), ("S", c_void_p), ("plan", POINTER(prism_probe_plan)),
+                ("plan_dev", c_void_p), ("out", c_void_p)]
+
+
 class PrismError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libprism error {code}: {msg}")
@@ -70,6 +75,9 @@ _SIGNATURES = {
                                  c_void_p], c_int32),
     "prism_probe_outputs": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p, c_int32,
                              c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
+    "prism_probe_batch_workspace": ([POINTER(prism_probe_job), c_int32, POINTER(c_size_t)], c_int32),
+    "prism_probe_outputs_batched": ([POINTER(prism_probe_job), c_int32, c_int32, c_void_p, c_size_t, c_void_p],
+                                    c_int32),
     "multislice_workspace": ([POINTER(prism_grid), c_int32, c_int64, POINTER(c_size_t)], c_int32),
     "multislice_outputs": ([POINTER(prism_grid), c_double, c_double, c_void_p, c_void_p, c_int64, c_double, c_int32,
                             c_int32, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),

@@ -12,7 +12,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from ._lib import (lib, check, prism_atom, prism_species, prism_grid, prism_smatrix_desc, prism_probe_plan,
-                   PRISM_FP32)
+                   prism_probe_job, PRISM_FP32)
 
 
 def _torch():
@@ -141,6 +141,33 @@ def prism_probe_outputs(d: prism_smatrix_desc, S, plan: ProbePlan, precision: in
     check(lib.prism_probe_outputs(ctypes.byref(d), _dev(S), ctypes.byref(p), _dev(plan.dev), int(precision),
                                   _dev(out), _dev(ws), ws.numel(), _stream()))
     return out
+
+
+def _jobs(items):
+    arr = (prism_probe_job * max(len(items), 1))()
+    for k, (d, S, plan, out) in enumerate(items):
+        arr[k].desc = ctypes.pointer(d)
+        arr[k].S = S.data_ptr()
+        arr[k].plan = ctypes.pointer(plan.plan)
+        arr[k].plan_dev = plan.dev.data_ptr()
+        arr[k].out = out.data_ptr()
+    return arr
+
+
+def prism_probe_batch_workspace(items) -> int:
+    """items: list of (desc, S, ProbePlan, out) tuples."""
+    need = ctypes.c_size_t()
+    check(lib.prism_probe_batch_workspace(_jobs(items), len(items), ctypes.byref(need)))
+    return need.value
+
+
+def prism_probe_outputs_batched(items, precision: int = PRISM_FP32, ws=None):
+    """Probe outputs of several (desc, S, ProbePlan, out) jobs in shared launches."""
+    arr = _jobs(items)
+    if ws is None:
+        ws = _workspace(prism_probe_batch_workspace(items), items[0][1].device if items else None)
+    check(lib.prism_probe_outputs_batched(arr, len(items), int(precision), _dev(ws), ws.numel(), _stream()))
+    return [it[3] for it in items]
 
 
 # ------------------------------------------------------------ multislice --

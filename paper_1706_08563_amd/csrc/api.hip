@@ -301,12 +301,28 @@ int batch_of(const prism_smatrix_desc* d) {
     return (d->beam_batch > 0 && d->beam_batch < d->n_beams) ? d->beam_batch : d->n_beams;
 }
 
+// Workspace of one probe-synthesis job: coefficients, windows and (for
+// windows above 128 pixels) intensities.
+size_t synth_job_bytes(const prism_smatrix_desc* d, const prism_probe_plan* plan, Carve& c) {
+    const size_t P = (size_t)std::max<int64_t>(plan->n_probes, 1);
+    const size_t before = c.off;
+    c.take<float2>(P * d->n_beams);
+    c.take<float2>(P * d->m_win * d->m_win);
+    if (d->m_win > 128) c.take<float>(P * d->m_win * d->m_win);
+    return c.off - before;
+}
+
+// Consistency of a descriptor filled by prism_smatrix_plan (without recounting
+// the beams, which costs O(n^2) host work per call).
 int check_desc(const prism_smatrix_desc* d) {
     if (!d) return fail(PRISM_E_INVAL, "descriptor is NULL");
-    prism_smatrix_desc c = *d;
-    int rc = prism_smatrix_plan(&c);
+    int rc = check_grid(&d->grid);
     if (rc) return rc;
-    if (c.n_beams != d->n_beams || c.ns != d->ns || c.m_win != d->m_win)
+    const int n = d->grid.n;
+    if (d->f < 1 || d->ns != n / 2 || d->ns % d->f != 0 || d->m_win != d->ns / d->f || d->n_beams < 1 ||
+        d->lambda != wavelength_A(d->E0) || d->sigma != sigma_per_VA(d->E0) ||
+        d->alpha_aa != alpha_aa_of(d->lambda, n, d->grid.cell[0]) ||
+        d->smatrix_bytes != (size_t)d->n_beams * d->ns * d->ns * sizeof(float2) || d->beam_batch < 0)
         return fail(PRISM_E_INVAL, "descriptor was not filled by prism_smatrix_plan");
     return PRISM_OK;
 }
@@ -541,9 +557,7 @@ int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, i
     p.off[7] = (size_t)c.take<int2>(h.beams.size());
     p.plan_bytes = c.off + 256;
     Carve w(nullptr);
-    w.take<float2>(P * d->n_beams);
-    w.take<float2>(P * d->m_win * d->m_win);
-    if (d->m_win > 128) w.take<float>(P * d->m_win * d->m_win);
+    synth_job_bytes(d, &p, w);
     p.ws_bytes = w.off + 256;
     *plan = p;
     return PRISM_OK;
@@ -575,43 +589,93 @@ int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
     return upload(plan_dev, blob, as_stream(stream));
 }
 
+static int synth_validate(const prism_probe_job* jobs, int n_jobs, int precision, size_t* need) {
+    if (!jobs || n_jobs < 0) return fail(PRISM_E_INVAL, "probe outputs: invalid job list");
+    if (precision != PRISM_FP32 && precision != PRISM_SPLIT_BF16X3 && precision != PRISM_BF16)
+        return fail(PRISM_E_INVAL, "probe outputs: unknown precision %d", precision);
+    Carve c(nullptr);
+    for (int k = 0; k < n_jobs; ++k) {
+        const prism_probe_job& jb = jobs[k];
+        int rc = check_desc(jb.desc);
+        if (rc) return rc;
+        if (!jb.S || !jb.plan || !jb.plan_dev || (!jb.out && jb.plan->n_probes > 0))
+            return fail(PRISM_E_INVAL, "probe outputs: job %d has a NULL pointer", k);
+        synth_job_bytes(jb.desc, jb.plan, c);
+    }
+    *need = c.off + 256;
+    return PRISM_OK;
+}
+
+// Probe synthesis for several (S-matrix, probe plan) jobs on one stream:
+// coefficients per job, one contraction launch for all jobs, one window
+// launch per window side.
+static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, void* ws, hipStream_t st) {
+    std::vector<ContractArgs> ca;
+    std::vector<std::vector<WindowArgs>> wa(10);   // by log2(m)
+    Carve c(ws);
+    for (int k = 0; k < n_jobs; ++k) {
+        const prism_probe_job& jb = jobs[k];
+        const prism_smatrix_desc* d = jb.desc;
+        const prism_probe_plan* plan = jb.plan;
+        const char* pb = static_cast<const char*>(jb.plan_dev);
+        const int P = (int)plan->n_probes, B = d->n_beams, M = d->m_win;
+        const size_t Pc = (size_t)std::max(P, 1);
+        float2* C = c.take<float2>(Pc * B);
+        float2* win = c.take<float2>(Pc * M * M);
+        float* inten = M > 128 ? c.take<float>(Pc * M * M) : nullptr;
+        if (P == 0) continue;
+        auto xy = reinterpret_cast<const double2*>(pb + plan->off[0]);
+        auto corner = reinterpret_cast<const int2*>(pb + plan->off[1]);
+        auto tstart = reinterpret_cast<const int*>(pb + plan->off[2]);
+        auto tprobes = reinterpret_cast<const int*>(pb + plan->off[3]);
+        auto perm = reinterpret_cast<const int*>(pb + plan->off[4]);
+        auto bstart = reinterpret_cast<const int*>(pb + plan->off[5]);
+        auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
+        auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
+        HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
+            return launch_coefficients(C, xy, beams, P, B, 1.0 / d->grid.cell[0], (float)(1.0 / std::sqrt((double)B)),
+                                       st);
+        }));
+        ca.push_back(ContractArgs{C, static_cast<const float2*>(jb.S), win, tstart, tprobes, corner, plan->n_tiles,
+                                  plan->max_per_tile, B, d->ns, M});
+        int lg = 0;
+        while ((1 << lg) < M) ++lg;
+        wa[lg].push_back(WindowArgs{win, inten, jb.out, perm, bstart, tw_m, P, plan->n_bins});
+    }
+    if (!ca.empty())
+        HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] { return launch_contract_batch(precision, ca.data(), (int)ca.size(), st); }));
+    for (int lg = 0; lg < 10; ++lg)
+        if (!wa[lg].empty())
+            HIP_TRY(timed(PRISM_K_WINDOW, st, [&] { return launch_window_batch(1 << lg, wa[lg].data(), (int)wa[lg].size(), st); }));
+    return PRISM_OK;
+}
+
 int prism_probe_outputs(const prism_smatrix_desc* d, const void* S, const prism_probe_plan* plan,
                         const void* plan_dev, int32_t precision, float* out, void* ws, size_t ws_bytes,
                         void* stream) {
-    int rc = check_desc(d);
+    prism_probe_job jb{d, S, plan, plan_dev, out};
+    size_t need = 0;
+    int rc = synth_validate(&jb, 1, precision, &need);
     if (rc) return rc;
-    if (!S || !plan || !plan_dev || !out) return fail(PRISM_E_INVAL, "probe outputs: NULL argument");
-    if (precision != PRISM_FP32 && precision != PRISM_SPLIT_BF16X3 && precision != PRISM_BF16)
-        return fail(PRISM_E_INVAL, "probe outputs: unknown precision %d", precision);
     if (!ws || ws_bytes < plan->ws_bytes)
         return fail(PRISM_E_WORKSPACE, "probe outputs: workspace %zu < %zu bytes", ws_bytes, plan->ws_bytes);
     if (plan->n_probes == 0) return PRISM_OK;
-    const char* pb = static_cast<const char*>(plan_dev);
-    auto xy = reinterpret_cast<const double2*>(pb + plan->off[0]);
-    auto corner = reinterpret_cast<const int2*>(pb + plan->off[1]);
-    auto tstart = reinterpret_cast<const int*>(pb + plan->off[2]);
-    auto tprobes = reinterpret_cast<const int*>(pb + plan->off[3]);
-    auto perm = reinterpret_cast<const int*>(pb + plan->off[4]);
-    auto bstart = reinterpret_cast<const int*>(pb + plan->off[5]);
-    auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
-    auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
-    const int P = (int)plan->n_probes, B = d->n_beams, M = d->m_win;
-    Carve c(ws);
-    float2* C = c.take<float2>((size_t)P * B);
-    float2* win = c.take<float2>((size_t)P * M * M);
-    float* inten = M > 128 ? c.take<float>((size_t)P * M * M) : nullptr;
-    hipStream_t st = as_stream(stream);
-    HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
-        return launch_coefficients(C, xy, beams, P, B, 1.0 / d->grid.cell[0], (float)(1.0 / std::sqrt((double)B)), st);
-    }));
-    HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] {
-        return launch_contract(precision, C, static_cast<const float2*>(S), win, tstart, tprobes, corner,
-                               plan->n_tiles, plan->max_per_tile, B, d->ns, M, st);
-    }));
-    HIP_TRY(timed(PRISM_K_WINDOW, st, [&] {
-        return launch_window_detect(M, win, inten, out, perm, bstart, tw_m, P, plan->n_bins, st);
-    }));
-    return PRISM_OK;
+    return synth_run(&jb, 1, precision, ws, as_stream(stream));
+}
+
+int prism_probe_batch_workspace(const prism_probe_job* jobs, int32_t n_jobs, size_t* bytes) {
+    if (!bytes) return fail(PRISM_E_INVAL, "batch workspace: NULL argument");
+    return synth_validate(jobs, n_jobs, PRISM_FP32, bytes);
+}
+
+int prism_probe_outputs_batched(const prism_probe_job* jobs, int32_t n_jobs, int32_t precision, void* ws,
+                                size_t ws_bytes, void* stream) {
+    size_t need = 0;
+    int rc = synth_validate(jobs, n_jobs, precision, &need);
+    if (rc) return rc;
+    if (!ws || ws_bytes < need)
+        return fail(PRISM_E_WORKSPACE, "batched probe outputs: workspace %zu < %zu bytes", ws_bytes, need);
+    return synth_run(jobs, n_jobs, precision, ws, as_stream(stream));
 }
 
 // ------------------------------------------------------------ multislice --

@@ -55,16 +55,33 @@ hipError_t launch_potential(float* V, int n, int n_slices, double L, const PotAt
 hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, int n_probes, int n_beams,
                                double inv_L, float amp, hipStream_t st);
 
-// Windowed contraction: win[p][v][u] = sum_b C[p][b] S[b][pix].
-hipError_t launch_contract(int precision, const float2* C, const float2* S, float2* win,
-                           const int* tile_start, const int* tile_probes, const int2* corner,
-                           int n_tiles, int max_per_tile, int n_beams, int ns, int m, hipStream_t st);
+// Windowed contraction of one probe set: win[p][v][u] = sum_b C[p][b] S[b][pix].
+struct ContractArgs {
+    const float2* C;
+    const float2* S;
+    float2* win;
+    const int* tile_start;
+    const int* tile_probes;
+    const int2* corner;
+    int n_tiles, max_per_tile, n_beams, ns, m;
+};
+// All jobs in as few launches as possible (one per 24 jobs).
+hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_jobs, hipStream_t st);
 
 // out[p][bin] = sum over the bin's pixels of |FFT_m(win[p])|^2 / m^4.  For
 // m > 128 the window is transformed in place and `inten` ([p][m*m] floats)
 // holds the intensities; for m <= 128 both stay untouched.
-hipError_t launch_window_detect(int m, float2* win, float* inten, float* out, const int* perm, const int* bin_start,
-                                const float2* tw_m, int n_probes, int n_bins, hipStream_t st);
+struct WindowArgs {
+    float2* win;
+    float* inten;
+    float* out;
+    const int* perm;
+    const int* bin_start;
+    const float2* tw_m;
+    int n_probes, n_bins;
+};
+// All jobs of one window side m (one launch per 24 jobs for m <= 128).
+hipError_t launch_window_batch(int m, const WindowArgs* jobs, int n_jobs, hipStream_t st);
 
 // out[p][bin] = sum over bin pixels of inten[p][pix] (deterministic order).
 hipError_t launch_bin_reduce(const float* inten, int64_t pix_per_item, float* out, const int* perm,

@@ -50,21 +50,63 @@ hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, 
 // window element is produced by exactly one (tile, probe) pair, so no atomics.
 constexpr int TILE = 16;
 
+// Work of one (request's) probe synthesis inside a batched contraction launch.
+struct ContractJob {
+    const float2* C;          // [n_probes][n_beams] coefficients
+    const float2* S;          // [n_beams][ns][ns]
+    float2* win;              // [n_probes][m][m]
+    const int* tile_start;    // [n_tiles + 1]
+    const int* tile_probes;
+    const int2* corner;       // window corner per probe
+    int n_beams, ns, m;
+    int chunks;               // workgroups per tile (probe chunks)
+    int n_tiles;
+    int block0;               // first logical workgroup of this job
+};
+constexpr int MAX_JOBS = 24;
+struct ContractBatch {
+    int n_jobs;
+    int n_blocks;             // logical workgroups over all jobs
+    int per_xcd;              // logical workgroups per XCD slot
+    ContractJob job[MAX_JOBS];
+};
+
+// Logical workgroup of this hardware workgroup.  Hardware workgroups are
+// dealt round-robin to the 8 XCDs; logical workgroups l and l+1 are placed on
+// the same XCD, so all probe chunks of a pixel tile share that XCD's L2.
+__device__ __forceinline__ const ContractJob* locate(const ContractBatch& b, int& tile, int& chunk) {
+    const int hw = blockIdx.x;
+    const int l = (hw & 7) * b.per_xcd + (hw >> 3);
+    if (l >= b.n_blocks) return nullptr;
+    int j = 0;
+    while (j + 1 < b.n_jobs && b.job[j + 1].block0 <= l) ++j;
+    const ContractJob* job = &b.job[j];
+    const int local = l - job->block0;
+    tile = local / job->chunks;
+    chunk = local % job->chunks;
+    return job;
+}
+
 namespace fp32c {
 constexpr int PC = 32;   // probes per workgroup
 constexpr int KB = 32;   // beams per LDS chunk
 }
 
-__global__ __launch_bounds__(WG) void k_contract_fp32(const float2* __restrict__ C, const float2* __restrict__ S,
-                                                      float2* __restrict__ win, const int* __restrict__ tile_start,
-                                                      const int* __restrict__ tile_probes,
-                                                      const int2* __restrict__ corner, int n_beams, int ns, int m) {
+__global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
     using namespace fp32c;
     __shared__ float2 cs[KB][PC];
     __shared__ int pidx[PC];
-    const int tile = blockIdx.x;
-    const int t0 = tile_start[tile], t1 = tile_start[tile + 1];
-    const int pc0 = t0 + (int)blockIdx.y * PC;
+    int tile, chunk;
+    const ContractJob* job = locate(batch, tile, chunk);
+    if (!job) return;
+    const float2* __restrict__ C = job->C;
+    const float2* __restrict__ S = job->S;
+    float2* __restrict__ win = job->win;
+    const int* __restrict__ tile_probes = job->tile_probes;
+    const int2* __restrict__ corner = job->corner;
+    const int n_beams = job->n_beams, ns = job->ns, m = job->m;
+    const int t0 = job->tile_start[tile], t1 = job->tile_start[tile + 1];
+    const int pc0 = t0 + chunk * PC;
     if (pc0 >= t1) return;
     const int np = min(PC, t1 - pc0);
     const int ntx = ns / TILE;
@@ -147,10 +189,7 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 template <bool SPLIT>
-__global__ __launch_bounds__(WG) void k_contract_mfma(const float2* __restrict__ C, const float2* __restrict__ S,
-                                                      float2* __restrict__ win, const int* __restrict__ tile_start,
-                                                      const int* __restrict__ tile_probes,
-                                                      const int2* __restrict__ corner, int n_beams, int ns, int m) {
+__global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
     using namespace mfmac;
     constexpr int NP = SPLIT ? 2 : 1;           // hi (, lo)
     // [part][re/im][row][beam]: 16 beams of a row contiguous (32 B)
@@ -158,9 +197,17 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(const float2* __restrict__
     __shared__ __attribute__((aligned(16))) unsigned short Cs[NP][2][PC][KB];
     __shared__ int pidx[PC];
 
-    const int tile = blockIdx.x;
-    const int t0 = tile_start[tile], t1 = tile_start[tile + 1];
-    const int pc0 = t0 + (int)blockIdx.y * PC;
+    int tile, chunk;
+    const ContractJob* job = locate(batch, tile, chunk);
+    if (!job) return;
+    const float2* __restrict__ C = job->C;
+    const float2* __restrict__ S = job->S;
+    float2* __restrict__ win = job->win;
+    const int* __restrict__ tile_probes = job->tile_probes;
+    const int2* __restrict__ corner = job->corner;
+    const int n_beams = job->n_beams, ns = job->ns, m = job->m;
+    const int t0 = job->tile_start[tile], t1 = job->tile_start[tile + 1];
+    const int pc0 = t0 + chunk * PC;
     if (pc0 >= t1) return;
     const int np = min(PC, t1 - pc0);
     const int ntx = ns / TILE;
@@ -295,24 +342,43 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(const float2* __restrict__
         }
 }
 
-hipError_t launch_contract(int precision, const float2* C, const float2* S, float2* win, const int* tile_start,
-                           const int* tile_probes, const int2* corner, int n_tiles, int max_per_tile, int n_beams,
-                           int ns, int m, hipStream_t st) {
-    if (precision == 0) {
-        using namespace fp32c;
-        dim3 grid((unsigned)n_tiles, (unsigned)((max_per_tile + PC - 1) / PC));
-        hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes, corner,
-                           n_beams, ns, m);
-    } else {
-        dim3 grid((unsigned)n_tiles, (unsigned)((max_per_tile + mfmac::PC - 1) / mfmac::PC));
-        if (precision == 1)
-            hipLaunchKernelGGL(k_contract_mfma<true>, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes,
-                               corner, n_beams, ns, m);
+hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_jobs, hipStream_t st) {
+    const int pc = precision == 0 ? fp32c::PC : mfmac::PC;
+    for (int j0 = 0; j0 < n_jobs; j0 += MAX_JOBS) {
+        ContractBatch b{};
+        b.n_jobs = n_jobs - j0 < MAX_JOBS ? n_jobs - j0 : MAX_JOBS;
+        int blocks = 0;
+        for (int k = 0; k < b.n_jobs; ++k) {
+            const ContractArgs& a = jobs[j0 + k];
+            ContractJob& job = b.job[k];
+            job.C = a.C;
+            job.S = a.S;
+            job.win = a.win;
+            job.tile_start = a.tile_start;
+            job.tile_probes = a.tile_probes;
+            job.corner = a.corner;
+            job.n_beams = a.n_beams;
+            job.ns = a.ns;
+            job.m = a.m;
+            job.chunks = (a.max_per_tile + pc - 1) / pc;
+            if (job.chunks < 1) job.chunks = 1;
+            job.n_tiles = a.n_tiles;
+            job.block0 = blocks;
+            blocks += job.chunks * job.n_tiles;
+        }
+        b.n_blocks = blocks;
+        b.per_xcd = (blocks + 7) / 8;
+        dim3 grid((unsigned)(8 * b.per_xcd));
+        if (precision == 0)
+            hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, b);
+        else if (precision == 1)
+            hipLaunchKernelGGL(k_contract_mfma<true>, grid, dim3(WG), 0, st, b);
         else
-            hipLaunchKernelGGL(k_contract_mfma<false>, grid, dim3(WG), 0, st, C, S, win, tile_start, tile_probes,
-                               corner, n_beams, ns, m);
+            hipLaunchKernelGGL(k_contract_mfma<false>, grid, dim3(WG), 0, st, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 // ------------------------------------------------ deterministic bin sums --
@@ -325,15 +391,35 @@ __device__ __forceinline__ float wave_sum(float v) {
 // ------------------------------------------------------- window detection --
 // One workgroup per probe: M x M window in LDS, row then column transforms,
 // |Psi|^2 / M^4, then each bin summed over its pixel list by one wavefront.
+struct WindowJob {
+    const float2* win;        // [n_probes][m][m]
+    float* out;               // [n_probes][n_bins]
+    const int* perm;          // window pixels grouped by bin
+    const int* bin_start;     // [n_bins + 1]
+    const float2* tw_m;       // W_m twiddles
+    int n_bins;
+    int probe0;               // first workgroup of this job
+};
+struct WindowBatch {
+    int n_jobs;
+    WindowJob job[MAX_JOBS];
+};
+
 template <int M>
-__global__ __launch_bounds__(WG) void k_window_detect(const float2* __restrict__ win, float* __restrict__ out,
-                                                      const int* __restrict__ perm,
-                                                      const int* __restrict__ bin_start,
-                                                      const float2* __restrict__ tw_m, int n_bins) {
+__global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
     using F = Fft<M>;
     constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, ROW = F::LDS + 1;
     __shared__ float2 buf[M * ROW];
-    const int p = blockIdx.x;
+    int jj = 0;
+    while (jj + 1 < batch.n_jobs && batch.job[jj + 1].probe0 <= (int)blockIdx.x) ++jj;
+    const WindowJob& job = batch.job[jj];
+    const float2* __restrict__ win = job.win;
+    float* __restrict__ out = job.out;
+    const int* __restrict__ perm = job.perm;
+    const int* __restrict__ bin_start = job.bin_start;
+    const float2* __restrict__ tw_m = job.tw_m;
+    const int n_bins = job.n_bins;
+    const int p = (int)blockIdx.x - job.probe0;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane / LPT, lt = lane % LPT;
     const float2* w = win + (size_t)p * M * M;
@@ -396,11 +482,22 @@ __global__ __launch_bounds__(WG) void k_window_detect(const float2* __restrict__
 }
 
 template <int M>
-static hipError_t window_m(const float2* win, float* out, const int* perm, const int* bin_start, const float2* tw_m,
-                           int n_probes, int n_bins, hipStream_t st) {
-    hipLaunchKernelGGL((k_window_detect<M>), dim3((unsigned)n_probes), dim3(WG), 0, st, win, out, perm, bin_start, tw_m,
-                       n_bins);
-    return hipGetLastError();
+static hipError_t window_m(const WindowArgs* jobs, int n_jobs, hipStream_t st) {
+    for (int j0 = 0; j0 < n_jobs; j0 += MAX_JOBS) {
+        WindowBatch b{};
+        b.n_jobs = n_jobs - j0 < MAX_JOBS ? n_jobs - j0 : MAX_JOBS;
+        int blocks = 0;
+        for (int k = 0; k < b.n_jobs; ++k) {
+            const WindowArgs& a = jobs[j0 + k];
+            b.job[k] = WindowJob{a.win, a.out, a.perm, a.bin_start, a.tw_m, a.n_bins, blocks};
+            blocks += a.n_probes;
+        }
+        if (blocks == 0) continue;
+        hipLaunchKernelGGL((k_window_detect<M>), dim3((unsigned)blocks), dim3(WG), 0, st, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------- large windows (M = 256, 512) --
@@ -484,15 +581,23 @@ static hipError_t window_large(float2* win, float* inten, float* out, const int*
     return launch_bin_reduce(inten, (int64_t)M * M, out, perm, bin_start, n_probes, n_bins, st);
 }
 
-hipError_t launch_window_detect(int m, float2* win, float* inten, float* out, const int* perm, const int* bin_start,
-                                const float2* tw_m, int n_probes, int n_bins, hipStream_t st) {
+hipError_t launch_window_batch(int m, const WindowArgs* jobs, int n_jobs, hipStream_t st) {
     switch (m) {
-        case 16: return window_m<16>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
-        case 32: return window_m<32>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
-        case 64: return window_m<64>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
-        case 128: return window_m<128>(win, out, perm, bin_start, tw_m, n_probes, n_bins, st);
-        case 256: return window_large<256>(win, inten, out, perm, bin_start, tw_m, n_probes, n_bins, st);
-        case 512: return window_large<512>(win, inten, out, perm, bin_start, tw_m, n_probes, n_bins, st);
+        case 16: return window_m<16>(jobs, n_jobs, st);
+        case 32: return window_m<32>(jobs, n_jobs, st);
+        case 64: return window_m<64>(jobs, n_jobs, st);
+        case 128: return window_m<128>(jobs, n_jobs, st);
+        case 256:
+        case 512:
+            for (int k = 0; k < n_jobs; ++k) {
+                const WindowArgs& a = jobs[k];
+                hipError_t e = m == 256 ? window_large<256>(a.win, a.inten, a.out, a.perm, a.bin_start, a.tw_m,
+                                                            a.n_probes, a.n_bins, st)
+                                        : window_large<512>(a.win, a.inten, a.out, a.perm, a.bin_start, a.tw_m,
+                                                            a.n_probes, a.n_bins, st);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
     }
     return hipErrorInvalidValue;
 }

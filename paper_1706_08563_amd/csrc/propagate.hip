@@ -40,6 +40,17 @@ constexpr int WG = 256;      // 4 wavefronts
 #ifndef PRISM_PASSB_WPE
 #define PRISM_PASSB_WPE 1
 #endif
+#ifndef PRISM_PASSB_COLS
+#define PRISM_PASSB_COLS 4       // adjacent columns per transform group in pass B (pipelined loads)
+#endif
+
+// Columns per pass-B transform group: pipelined when the column count allows.
+template <int N, int MODE>
+struct PassBCols {
+    static constexpr int CPB = 4 * (64 / Fft<N / 2>::LPT);
+    static constexpr int value =
+        (MODE != PASSB_INIT && (N / 2) % (CPB * PRISM_PASSB_COLS) == 0) ? PRISM_PASSB_COLS : 1;
+};
 
 template <int N>
 struct RowCfg {
@@ -214,17 +225,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
     using F = Fft<N / 2>;
     constexpr int L = N / 2, E = F::E, LPT = F::LPT, G = 64 / LPT, CPB = 4 * G;
     constexpr int NB = PRISM_PASSB_ILP ? 2 : 1;
+    constexpr int NC = PassBCols<N, MODE>::value;   // adjacent columns per transform group
     __shared__ float2 xch[NB * CPB * F::LDS];
 
     const int item = blockIdx.x % n_items;
     const int cb = blockIdx.x / n_items;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane / LPT, lt = lane % LPT;
-    const int j = cb * CPB + wave * G + g;
-    if (j >= L) return;                          // whole transform groups exit together
+    const int j0 = (cb * CPB + wave * G + g) * NC;
+    if (j0 >= L) return;                         // whole transform groups exit together
     float2* lds = xch + (wave * G + g) * F::LDS;
     float2* lds2 = xch + ((NB - 1) * CPB + wave * G + g) * F::LDS;
-    const int kxj = j < N / 4 ? j : j - N / 2;
 
     typename F::Twiddles tw;
     tw.load(tb.tw_half, lt);
@@ -232,12 +243,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
 #pragma unroll
     for (int i = 0; i < E; ++i) btw[i] = tb.band_tw[lt + LPT * i];
 
-    float2* col = W + ((size_t)item * L + j) * wave_col_stride(N);
-    float4* col4 = reinterpret_cast<float4*>(col);
+    float2* const Wi = W + (size_t)item * L * wave_col_stride(N);
     float2 e[E], o[E];
 
     if constexpr (MODE == PASSB_INIT) {
         // aperture spectrum of the probe at (x, y): amp e^{-2 pi i (kx x + ky y) / L}
+        const int j = j0;
+        const int kxj = j < N / 4 ? j : j - N / 2;
+        float4* col4 = reinterpret_cast<float4*>(Wi + (size_t)j * wave_col_stride(N));
         const double2 p = probe_xy[item];
         const int kym = ky_max[j];
         const double ax = (double)kxj * p.x * inv_L;
@@ -265,59 +278,80 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
 #pragma unroll
         for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
         return;
-    }
-
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        float4 v = col4[lt + LPT * i];
-        e[i] = make_float2(v.x, v.y);
-        o[i] = make_float2(v.z, v.w);
-    }
-    if constexpr (PRISM_PASSB_ILP) {
-        F::template run2<-1>(e, o, lds, lds2, tw, lt);
     } else {
-        F::template run<-1>(e, lds, tw, lt);
-        F::template run<-1>(o, lds, tw, lt);
-    }
-    const float2 pj = tb.prop[j];
+        // software pipeline over NC columns: the next column's loads are in
+        // flight while this one is transformed
+        float4 cur[E], nxt[E];
+        {
+            const float4* c4 = reinterpret_cast<const float4*>(Wi + (size_t)j0 * wave_col_stride(N));
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        int jp = lt + LPT * i;
-        int ky = jp < N / 4 ? jp : jp - N / 2;
-        float2 psi = cadd(e[i], cmul(btw[i], o[i]));
-        bool in = 16 * (kxj * kxj + ky * ky) < N * N;
-        e[i] = in ? cmul(psi, cmul(pj, tb.prop[jp])) : make_float2(0.f, 0.f);
-    }
-    if constexpr (MODE == PASSB_LAST_I) {
-        float* dst = inten + ((size_t)item * L + j) * L;
+            for (int i = 0; i < E; ++i) cur[i] = c4[lt + LPT * i];
+        }
 #pragma unroll
-        for (int i = 0; i < E; ++i) dst[lt + LPT * i] = cnorm(e[i]);
-        return;
-    }
-    if constexpr (MODE == PASSB_LAST_S) {
-        // even rows only: psi(2 my) for my in [0, n/2), written over the
-        // first half of this (already loaded) column
-        F::template run<+1>(e, lds, tw, lt);
+        for (int c = 0; c < NC; ++c) {
+            const int j = j0 + c;
+            float2* col = Wi + (size_t)j * wave_col_stride(N);
+            float4* col4 = reinterpret_cast<float4*>(col);
+            if (c + 1 < NC) {
+                const float4* n4 = reinterpret_cast<const float4*>(col + wave_col_stride(N));
 #pragma unroll
-        for (int i = 0; i < E; ++i) col[lt + LPT * i] = e[i];
-        return;
-    }
+                for (int i = 0; i < E; ++i) nxt[i] = n4[lt + LPT * i];
+            }
+            const int kxj = j < N / 4 ? j : j - N / 2;
 #pragma unroll
-    for (int i = 0; i < E; ++i) o[i] = cmulc(e[i], btw[i]);
-    if constexpr (PRISM_PASSB_ILP) {
-        F::template run2<+1>(e, o, lds, lds2, tw, lt);
-    } else {
-        F::template run<+1>(e, lds, tw, lt);
-        F::template run<+1>(o, lds, tw, lt);
-    }
+            for (int i = 0; i < E; ++i) {
+                e[i] = make_float2(cur[i].x, cur[i].y);
+                o[i] = make_float2(cur[i].z, cur[i].w);
+            }
+            if constexpr (PRISM_PASSB_ILP) {
+                F::template run2<-1>(e, o, lds, lds2, tw, lt);
+            } else {
+                F::template run<-1>(e, lds, tw, lt);
+                F::template run<-1>(o, lds, tw, lt);
+            }
+            const float2 pj = tb.prop[j];
 #pragma unroll
-    for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
+            for (int i = 0; i < E; ++i) {
+                int jp = lt + LPT * i;
+                int ky = jp < N / 4 ? jp : jp - N / 2;
+                float2 psi = cadd(e[i], cmul(btw[i], o[i]));
+                bool in = 16 * (kxj * kxj + ky * ky) < N * N;
+                e[i] = in ? cmul(psi, cmul(pj, tb.prop[jp])) : make_float2(0.f, 0.f);
+            }
+            if constexpr (MODE == PASSB_LAST_I) {
+                float* dst = inten + ((size_t)item * L + j) * L;
+#pragma unroll
+                for (int i = 0; i < E; ++i) dst[lt + LPT * i] = cnorm(e[i]);
+            } else if constexpr (MODE == PASSB_LAST_S) {
+                // even rows only: psi(2 my) for my in [0, n/2), written over the
+                // first half of this (already loaded) column
+                F::template run<+1>(e, lds, tw, lt);
+#pragma unroll
+                for (int i = 0; i < E; ++i) col[lt + LPT * i] = e[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < E; ++i) o[i] = cmulc(e[i], btw[i]);
+                if constexpr (PRISM_PASSB_ILP) {
+                    F::template run2<+1>(e, o, lds, lds2, tw, lt);
+                } else {
+                    F::template run<+1>(e, lds, tw, lt);
+                    F::template run<+1>(o, lds, tw, lt);
+                }
+#pragma unroll
+                for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
+            }
+            if (c + 1 < NC) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) cur[i] = nxt[i];
+            }
+        }
+    }
 }
 
 template <int N, int MODE>
 static hipError_t pass_b_nm(float2* W, const PropTables& tb, float2* out_half, float* inten, const int* ky_max,
                             const double2* xy, double inv_L, float amp, int n_items, hipStream_t st) {
-    constexpr int L = N / 2, LPT = Fft<L>::LPT, CPB = 4 * (64 / LPT);
+    constexpr int L = N / 2, LPT = Fft<L>::LPT, CPB = 4 * (64 / LPT) * PassBCols<N, MODE>::value;
     dim3 grid((unsigned)((size_t)n_items * ((L + CPB - 1) / CPB)));
     hipLaunchKernelGGL((k_pass_b<N, MODE>), grid, dim3(WG), 0, st, W, tb, out_half, inten, ky_max, xy, inv_L, amp,
                        n_items);

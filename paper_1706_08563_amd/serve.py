@@ -1,0 +1,329 @@
+"""Continuous-batching request loop for PRISM simulations on one GPU.
+
+Requests (a cell, grid size, interpolation factor, slice count and probe
+scan each) arrive over time.  The loop
+
+* admits a request when its HBM footprint fits the free budget (the analogue
+  of choosing a memory model from a device-memory estimate, "Streaming Data
+  for Very Large Simulations"), first come first served with bypass: a later
+  request that fits may pass a waiting one, until the waiting one has been
+  passed `aging` times;
+* builds each admitted request's potential and S-matrix on that request's own
+  HIP stream, so builds of different requests overlap on the device;
+* keeps every built S-matrix resident until its probes are done, and
+  synthesises probes of all built requests together: each scheduling step
+  issues one batched synthesis (prism_probe_outputs_batched) over up to
+  `max_jobs` probe chunks from different requests on a synthesis stream;
+* returns each request's detector outputs and records its latency from
+  arrival to host-side result.
+
+`Scheduler` holds the policy and no device state, so it is exercised on the
+CPU with a fake executor; `GpuExecutor` drives the library.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# --------------------------------------------------------------- requests --
+@dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds since the start of the stream
+    n: int                         # grid side
+    f: int                         # interpolation factor
+    n_slices: int
+    scan: tuple                    # (nx, ny)
+    seed: int
+    E0: float = 200e3
+    alpha_max: float = 0.02
+    dalpha: float = 1e-3
+    pixel: float = 0.09765625      # A per pixel (cell side = n * pixel)
+    # the specimen: (positions [n, 3] A, species index [n], species list) or a
+    # callable returning that tuple (called when the request is admitted)
+    sample: object = None
+    # filled while serving
+    state: str = "queued"          # queued -> building -> built -> done | rejected | cancelled
+    footprint: int = 0
+    skipped: int = 0
+    chunks_total: int = 0
+    chunks_done: int = 0
+    chunks_issued: int = 0
+    t_admit: float = math.nan
+    t_built: float = math.nan
+    t_done: float = math.nan
+    result: object = None
+    info: dict = field(default_factory=dict)
+
+    @property
+    def cell(self):
+        L = self.n * self.pixel
+        return (L, L, 2.0 * self.n_slices)
+
+    @property
+    def n_probes(self):
+        return self.scan[0] * self.scan[1]
+
+    @property
+    def latency(self):
+        return self.t_done - self.arrival
+
+
+# --------------------------------------------------------------- scheduler --
+class Scheduler:
+    """Admission, bookkeeping and batch formation; no device state."""
+
+    def __init__(self, capacity: int, max_building: int = 4, max_jobs: int = 24, aging: int = 8):
+        self.capacity = int(capacity)
+        self.used = 0
+        self.max_building = max_building
+        self.max_jobs = max_jobs
+        self.aging = aging
+        self.queue: list[Request] = []
+        self.building: list[Request] = []
+        self.built: list[Request] = []
+        self.done: list[Request] = []
+        self.rejected: list[Request] = []
+        self.peak_used = 0
+
+    def arrive(self, req: Request, footprint: int):
+        req.footprint = int(footprint)
+        if req.footprint > self.capacity:
+            req.state = "rejected"
+            self.rejected.append(req)
+            return False
+        self.queue.append(req)
+        return True
+
+    def cancel(self, req: Request) -> bool:
+        """Cancel a request that has not been admitted yet."""
+        if req in self.queue:
+            self.queue.remove(req)
+            req.state = "cancelled"
+            return True
+        return False
+
+    def admit(self, now: float) -> list:
+        """Requests to start now: first come first served; a later request that
+        fits may pass waiting ones, each of which counts that bypass; once a
+        waiting request has been passed `aging` times nobody passes it."""
+        out = []
+        waiting = []                    # earlier requests that did not fit
+        for req in list(self.queue):
+            if len(self.building) + len(out) >= self.max_building:
+                break
+            if self.used + req.footprint <= self.capacity:
+                if any(w.skipped >= self.aging for w in waiting):
+                    break
+                for w in waiting:
+                    w.skipped += 1
+                self.queue.remove(req)
+                self.used += req.footprint
+                self.peak_used = max(self.peak_used, self.used)
+                req.state = "building"
+                req.t_admit = now
+                out.append(req)
+            else:
+                waiting.append(req)
+        self.building.extend(out)
+        return out
+
+    def fail(self, req: Request, now: float, reason: str):
+        """A request whose device work could not start (e.g. allocation failure)."""
+        if req in self.building:
+            self.building.remove(req)
+            self.used -= req.footprint
+        req.state = "failed"
+        req.t_done = now
+        req.info["error"] = reason
+        self.rejected.append(req)
+
+    def mark_built(self, req: Request, now: float):
+        self.building.remove(req)
+        req.state = "built"
+        req.t_built = now
+        self.built.append(req)
+
+    def next_batch(self, chunks_left) -> list:
+        """Up to max_jobs (request, chunk index) pairs from built requests,
+        oldest request first.  `chunks_left(req)` gives the chunks not yet issued."""
+        batch = []
+        for req in sorted(self.built, key=lambda r: r.arrival):
+            for c in chunks_left(req):
+                if len(batch) >= self.max_jobs:
+                    return batch
+                batch.append((req, c))
+        return batch
+
+    def chunk_done(self, req: Request, now: float) -> bool:
+        req.chunks_done += 1
+        if req.chunks_done == req.chunks_total:
+            self.built.remove(req)
+            self.used -= req.footprint
+            req.state = "done"
+            req.t_done = now
+            self.done.append(req)
+            return True
+        return False
+
+    @property
+    def idle(self):
+        return not (self.queue or self.building or self.built)
+
+
+# --------------------------------------------------------------- GPU side --
+class GpuExecutor:
+    """Runs requests with libprism on the current HIP device."""
+
+    def __init__(self, precision: int, probe_chunk_bytes: int = 1 << 30, build_ws_bytes: int = 16 << 30):
+        import torch
+
+        from . import api
+        from ._lib import PRISM_FP32  # noqa: F401
+        self.torch = torch
+        self.api = api
+        self.precision = precision
+        self.probe_chunk_bytes = probe_chunk_bytes
+        self.build_ws_bytes = build_ws_bytes
+        self.synth_stream = torch.cuda.Stream()
+        self.inflight = []              # (event, [(req, chunk)], ws)
+
+    # -- planning (host) --
+    def plan(self, req: Request):
+        """Descriptors, beam batch and probe chunks of a request; returns its footprint."""
+        api = self.api
+        g = api.prism_grid_init(req.cell, 2.0, req.n)
+        d = api.prism_smatrix_plan(g, req.E0, req.alpha_max, req.f)
+        per_beam = (d.build_ws_bytes - 0) // max(d.n_beams, 1)
+        bb = max(1, min(d.n_beams, self.build_ws_bytes // max(per_beam, 1)))
+        if bb < d.n_beams:
+            d = api.prism_smatrix_plan(g, req.E0, req.alpha_max, req.f, beam_batch=bb)
+        nx, ny = req.scan
+        xs = np.arange(nx) * (req.cell[0] / nx)
+        ys = np.arange(ny) * (req.cell[1] / ny)
+        yy, xx = np.meshgrid(ys, xs, indexing="ij")
+        xy = np.stack([xx.ravel(), yy.ravel()], axis=1)
+        per_probe = d.n_beams * 8 + d.m_win * d.m_win * (12 if d.m_win > 128 else 8)
+        pc = max(1, min(len(xy), self.probe_chunk_bytes // per_probe))
+        chunks = [xy[i:i + pc] for i in range(0, len(xy), pc)]
+        plans = [api.prism_probe_plan_init(d, c, req.dalpha) for c in chunks]
+        n_bins = plans[0].n_bins
+        foot = (g.n_slices * g.n * g.n * 4 + d.smatrix_bytes + d.build_ws_bytes
+                + sum(p.plan_bytes for p in plans) + max(p.ws_bytes for p in plans) + len(xy) * n_bins * 4)
+        req.info.update(grid=g, desc=d, chunks=chunks, n_bins=n_bins, n_beams=d.n_beams, m_win=d.m_win,
+                        beam_batch=d.beam_batch or d.n_beams)
+        req.chunks_total = len(chunks)
+        return int(foot)
+
+    # -- build --
+    def start(self, req: Request):
+        torch, api = self.torch, self.api
+        info = req.info
+        st = torch.cuda.Stream()
+        info["stream"] = st
+        pos, sp, species = req.sample() if callable(req.sample) else req.sample
+        with torch.cuda.stream(st):
+            info["plans"] = [api.prism_probe_plan_upload(info["desc"], c, req.dalpha) for c in info["chunks"]]
+            V = api.prism_project_potential(pos, sp, species, info["grid"])
+            ws = torch.empty(info["desc"].build_ws_bytes, dtype=torch.uint8, device="cuda")
+            S = api.prism_build_smatrix(info["desc"], V, ws=ws)
+            info["out"] = torch.empty((req.n_probes, info["n_bins"]), dtype=torch.float32, device="cuda")
+            ev = torch.cuda.Event()
+            ev.record(st)
+        ws.record_stream(st)
+        V.record_stream(st)
+        del ws, V
+        info["S"] = S
+        info["built_event"] = ev
+
+    def is_built(self, req: Request) -> bool:
+        return req.info["built_event"].query()
+
+    # -- synthesis --
+    def synthesize(self, batch):
+        """Issue one batched synthesis for [(req, chunk)] on the synthesis stream."""
+        torch, api = self.torch, self.api
+        items = []
+        for req, c in batch:
+            info = req.info
+            self.synth_stream.wait_event(info["built_event"])
+            p0 = sum(len(x) for x in info["chunks"][:c])
+            out = info["out"][p0:p0 + len(info["chunks"][c])]
+            items.append((info["desc"], info["S"], info["plans"][c], out))
+            req.chunks_issued += 1
+        with torch.cuda.stream(self.synth_stream):
+            ws = torch.empty(max(api.prism_probe_batch_workspace(items), 1), dtype=torch.uint8, device="cuda")
+            api.prism_probe_outputs_batched(items, self.precision, ws=ws)
+            ev = torch.cuda.Event()
+            ev.record(self.synth_stream)
+        self.inflight.append((ev, list(batch), ws))
+
+    def finished_batches(self):
+        """Batches whose synthesis completed (in issue order)."""
+        done = []
+        while self.inflight and self.inflight[0][0].query():
+            ev, batch, ws = self.inflight.pop(0)
+            done.append(batch)
+        return done
+
+    def collect(self, req: Request):
+        info = req.info
+        req.result = info["out"].cpu().numpy()
+        for k in ("S", "out", "plans"):
+            info.pop(k, None)
+
+    def chunks_left(self, req: Request):
+        return range(req.chunks_issued, req.chunks_total)
+
+
+# ---------------------------------------------------------------- the loop --
+def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, idle_sleep=2e-4, on_done=None,
+          sleep=time.sleep):
+    """Run the request stream to completion; returns the scheduler."""
+    pending = sorted(requests, key=lambda r: r.arrival)
+    t0 = clock()
+    i = 0
+    while i < len(pending) or not scheduler.idle or getattr(executor, "inflight", None):
+        now = clock() - t0
+        while i < len(pending) and pending[i].arrival <= now:
+            req = pending[i]
+            scheduler.arrive(req, executor.plan(req))
+            i += 1
+        for req in scheduler.admit(now):
+            try:
+                executor.start(req)
+            except (MemoryError, RuntimeError) as exc:    # e.g. device allocation failure
+                scheduler.fail(req, clock() - t0, str(exc))
+        for req in list(scheduler.building):
+            if executor.is_built(req):
+                scheduler.mark_built(req, clock() - t0)
+        if not executor.inflight:
+            batch = scheduler.next_batch(executor.chunks_left)
+            if batch:
+                executor.synthesize(batch)
+        progressed = False
+        for batch in executor.finished_batches():
+            progressed = True
+            for req, _ in batch:
+                if scheduler.chunk_done(req, clock() - t0):
+                    executor.collect(req)
+                    req.t_done = clock() - t0
+                    if on_done:
+                        on_done(req)
+        if not progressed:
+            sleep(idle_sleep)
+    return scheduler
+
+
+def summarize(sched: Scheduler, wall: float):
+    done = sched.done
+    lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+    probes = sum(r.n_probes for r in done)
+    return {"requests": len(done), "rejected": len(sched.rejected), "probes": probes,
+            "wall_s": wall, "probes_per_s": probes / wall if wall > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "peak_hbm_reserved": sched.peak_used}

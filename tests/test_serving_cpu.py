@@ -1,0 +1,143 @@
+"""Serving policy on the CPU: a fake executor with a fake clock stands in for
+the GPU (admission by footprint, bypass with aging, cancellation, failures,
+cross-request batches and out-of-order completion)."""
+import pytest
+
+from paper_1706_08563_amd.serve import Request, Scheduler, serve
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-3)
+
+
+class FakeExecutor:
+    """Build time and footprint come from the request; synthesis of a batch
+    takes 1 ms per chunk."""
+
+    def __init__(self, clock, fail_ids=()):
+        self.clock = clock
+        self.inflight = []
+        self.batches = []
+        self.fail_ids = set(fail_ids)
+        self.live = 0
+        self.max_live = 0
+
+    def plan(self, req):
+        req.chunks_total = req.info.get("chunks", 1)
+        return req.info["foot"]
+
+    def start(self, req):
+        if req.rid in self.fail_ids:
+            raise MemoryError("fake allocation failure")
+        req.info["built_at"] = self.clock() + req.info.get("build", 0.01)
+        self.live += req.footprint
+        self.max_live = max(self.max_live, self.live)
+
+    def is_built(self, req):
+        return self.clock() >= req.info["built_at"]
+
+    def chunks_left(self, req):
+        return range(req.chunks_issued, req.chunks_total)
+
+    def synthesize(self, batch):
+        for req, _ in batch:
+            req.chunks_issued += 1
+        self.batches.append([(r.rid, c) for r, c in batch])
+        self.inflight.append((self.clock() + 1e-3 * len(batch), list(batch)))
+
+    def finished_batches(self):
+        done = []
+        while self.inflight and self.inflight[0][0] <= self.clock():
+            done.append(self.inflight.pop(0)[1])
+        return done
+
+    def collect(self, req):
+        req.result = req.rid
+        self.live -= req.footprint
+
+
+def _req(rid, t, foot, build=0.01, chunks=1):
+    r = Request(rid, t, 256, 2, 10, (4, 4), rid)
+    r.info.update(foot=foot, build=build, chunks=chunks)
+    return r
+
+
+def _run(reqs, capacity, **kw):
+    clk = Clock()
+    ex = FakeExecutor(clk, kw.pop("fail_ids", ()))
+    sched = Scheduler(capacity, **kw)
+    serve(reqs, ex, sched, clock=clk, sleep=clk.sleep)
+    return sched, ex
+
+
+def test_admission_never_exceeds_budget_and_all_complete():
+    reqs = [_req(i, 0.001 * i, foot=10 + (i % 5) * 20) for i in range(40)]
+    sched, ex = _run(reqs, capacity=100, max_building=3)
+    assert len(sched.done) == 40 and not sched.rejected
+    assert sched.peak_used <= 100 and ex.max_live <= 100
+    assert sched.used == 0
+    assert all(r.latency >= 0 and r.t_admit >= r.arrival for r in reqs)
+
+
+def test_over_budget_request_is_rejected():
+    reqs = [_req(0, 0.0, foot=50), _req(1, 0.0, foot=500), _req(2, 0.0, foot=50)]
+    sched, _ = _run(reqs, capacity=100)
+    assert [r.rid for r in sched.rejected] == [1] and reqs[1].state == "rejected"
+    assert {r.rid for r in sched.done} == {0, 2}
+
+
+def test_bypass_then_aging_prevents_starvation():
+    # one large request behind a long stream of small ones that keep the budget busy
+    reqs = [_req(0, 0.0, foot=60, build=0.05)]
+    reqs += [_req(1, 0.0005, foot=90, build=0.02)]
+    reqs += [_req(i, 0.001 + 0.002 * i, foot=30, build=0.02) for i in range(2, 60)]
+    sched, _ = _run(reqs, capacity=100, max_building=8, aging=3)
+    big = reqs[1]
+    assert big.state == "done"
+    # it was passed by some small requests, but not by all of them
+    passed = [r for r in reqs[2:] if r.t_admit < big.t_admit]
+    assert 0 < len(passed) < 58
+
+
+def test_cancel_queued_request():
+    sched = Scheduler(100)
+    a, b = _req(0, 0.0, 80), _req(1, 0.0, 80)
+    sched.arrive(a, 80)
+    sched.arrive(b, 80)
+    assert sched.admit(0.0) == [a]
+    assert sched.cancel(b) and b.state == "cancelled"
+    assert not sched.cancel(a)          # already admitted
+    assert sched.queue == []
+
+
+def test_allocation_failure_releases_budget():
+    reqs = [_req(i, 0.0, foot=40) for i in range(5)]
+    sched, _ = _run(reqs, capacity=100, fail_ids={1, 3})
+    assert {r.rid for r in sched.done} == {0, 2, 4}
+    assert {r.rid for r in sched.rejected} == {1, 3}
+    assert all(r.state == "failed" and "allocation" in r.info["error"] for r in (reqs[1], reqs[3]))
+    assert sched.used == 0
+
+
+def test_batches_mix_requests_and_respect_max_jobs():
+    reqs = [_req(i, 0.0, foot=10, chunks=3, build=0.01) for i in range(6)]
+    sched, ex = _run(reqs, capacity=100, max_building=6, max_jobs=5)
+    assert all(len(b) <= 5 for b in ex.batches)
+    assert any(len({rid for rid, _ in b}) > 1 for b in ex.batches)
+    issued = sorted(x for b in ex.batches for x in b)
+    assert issued == sorted((i, c) for i in range(6) for c in range(3))
+
+
+def test_out_of_order_completion():
+    # a slow early request and a fast later one: the later one finishes first
+    reqs = [_req(0, 0.0, foot=40, build=0.5), _req(1, 0.01, foot=40, build=0.01)]
+    sched, _ = _run(reqs, capacity=100)
+    assert reqs[1].t_done < reqs[0].t_done
+    assert [r.rid for r in sched.done] == [1, 0]

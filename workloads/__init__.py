@@ -172,3 +172,33 @@ def small_workload(n=64, cell=(10.0, 10.0, 6.0), dz=2.0, E0=80e3, alpha_max=0.02
     w = Workload(f"small_{n}", tuple(cell), n, dz, E0, alpha_max, f, scan,
                  (SC1, AU), seed=seed, structure="given")
     return w, pos, species
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: Poisson arrivals of mixed simulations.
+# ---------------------------------------------------------------------------
+def serving_stream(n_requests: int, rate: float, seed: int = 4, grids=(256, 512, 1024, 2048), fs=(2, 4, 8),
+                   slices=(10, 50), scan=(16, 128)):
+    """Request parameters (dicts) with Poisson arrival times (rate per second).
+
+    Grid from `grids`, interpolation factor from `fs`, slice count uniform in
+    `slices`, square scan side uniform in `scan`; the cell of request i is the
+    nanoparticle-in-amorphous recipe seeded with 1000 + i.
+    """
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_requests)) if rate > 0 else np.zeros(n_requests)
+    out = []
+    for i in range(n_requests):
+        s = int(rng.integers(scan[0], scan[1] + 1))
+        out.append(dict(rid=i, arrival=float(t[i]), n=int(rng.choice(grids)), f=int(rng.choice(fs)),
+                        n_slices=int(rng.integers(slices[0], slices[1] + 1)), scan=(s, s), seed=1000 + i))
+    return out
+
+
+def serving_sample(cell, seed: int):
+    """Callable giving the specimen of a serving request: the nanoparticle in
+    an amorphous matrix of config 1, scaled to `cell`, seeded with `seed`."""
+    def make():
+        pos, sp = nanoparticle_in_amorphous(cell, rng=np.random.default_rng(seed))
+        return pos, sp, (AU, C)
+    return make
