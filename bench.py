@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=40)
     ap.add_argument("--load", type=float, default=0.8, help="offered load against the modelled capacity")
     ap.add_argument("--grids", default="256,512,1024,2048")
+    ap.add_argument("--precision-study", action="store_true", help="2048^2 f=8 contraction precision study")
     return ap.parse_args()
 
 
@@ -170,6 +171,95 @@ def run_serving(args):
     print(json.dumps(res), flush=True)
 
 
+def multislice_leg(args):
+    """Plain multislice on the 1024^2 nanoparticle cell: 64 x 64 probes, 50
+    slices, probes propagated 1024 at a time (the comparison method)."""
+    import numpy as np
+    import torch
+
+    import paper_1706_08563_amd as P
+    import workloads as W
+
+    w = W.CONFIGS[1]
+    pos, sp = W.atoms_for(w)
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    V = P.prism_project_potential(pos, sp, w.species, g)
+    xy = W.scan_positions(w.cell, *w.scan)
+    batch = 1024
+    ws = torch.empty(P.multislice_workspace(g, batch, len(xy)), dtype=torch.uint8, device="cuda")
+    out = torch.empty((len(xy), 65), dtype=torch.float32, device="cuda")
+    P.multislice_outputs(g, w.E0, w.alpha_max, V, xy[:batch], batch=batch, ws=ws, out=out[:batch])
+    torch.cuda.synchronize()
+    P.prism_timing_reset()
+    P.prism_timing_enable(True)
+    t0 = time.perf_counter()
+    P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=batch, ws=ws, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P.prism_timing_enable(False)
+    kt = {k: P.prism_timing_read(c) for k, c in P.TIMING_CLASSES.items()}
+    N2 = float(w.n) ** 2
+    a_ms = kt["pass_a"][0] / max(kt["pass_a"][1], 1)
+    b_ms = kt["pass_b"][0] / max(kt["pass_b"][1], 1)
+    return {"workload": w.name, "probes": len(xy), "slices": g.n_slices, "grid": w.n, "batch": batch,
+            "seconds": dt, "probes_per_s": len(xy) / dt,
+            "pass_a_avg_ms": a_ms, "pass_b_avg_ms": b_ms,
+            "pass_a_GB_per_s": (batch * 8 * N2 + 8 * N2) / (a_ms * 1e-3) / 1e9,
+            "pass_b_GB_per_s": batch * 8 * N2 / (b_ms * 1e-3) / 1e9}
+
+
+def precision_study(args):
+    """Windowed contraction three ways (split-BF16, BF16, FP32) on the 2048^2,
+    f = 8 geometry (1245 beams, 128^2 windows, 256 x 256 scan): device time per
+    variant over the full scan, and error against the FP64 oracle on a 16 x 16
+    probe subset.  The S-matrix operand is seeded complex-normal noise (the
+    contraction's accuracy does not depend on where S came from; noise has no
+    structure that could hide an error)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import paper_1706_08563_amd as P
+    import workloads as W
+
+    w = W.CONFIGS[3]
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    rng = np.random.default_rng(303)
+    log(f"precision study: S {d.n_beams} x {d.ns}^2 random operand")
+    S = torch.empty((d.n_beams, d.ns, d.ns), dtype=torch.complex64, device="cuda")
+    for b0 in range(0, d.n_beams, 64):
+        S[b0:b0 + 64] = torch.from_numpy(W.random_complex((min(64, d.n_beams - b0), d.ns, d.ns), rng)).cuda()
+    xy = W.scan_positions(w.cell, *w.scan)
+    sub = W.scan_positions(w.cell, *w.scan, sub=w.scan[0] // 16)
+    plan = P.prism_probe_plan_upload(d, xy)
+    plan_s = P.prism_probe_plan_upload(d, sub)
+    ws = torch.empty(plan.plan.ws_bytes, dtype=torch.uint8, device="cuda")
+    beams = P.prism_beam_list(d).astype(np.int64)
+    Sh = S.cpu().numpy()
+    log("oracle on the 16 x 16 subset")
+    ref = O.prism_outputs(Sh, beams, w.cell[0], w.n, d.lambda_, w.f, sub)
+    res = {"workload": w.name, "probes_timed": len(xy), "probes_checked": len(sub), "beams": d.n_beams}
+    for name, prec in (("bf16x3", P.PRISM_SPLIT_BF16X3), ("bf16", P.PRISM_BF16), ("fp32", P.PRISM_FP32)):
+        out = P.prism_probe_outputs(d, S, plan, prec, ws=ws)
+        torch.cuda.synchronize()
+        P.prism_timing_reset()
+        P.prism_timing_enable(True)
+        t0 = time.perf_counter()
+        P.prism_probe_outputs(d, S, plan, prec, ws=ws, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        P.prism_timing_enable(False)
+        cms, _ = P.prism_timing_read(P.TIMING_CLASSES["contract"])
+        got = P.prism_probe_outputs(d, S, plan_s, prec).cpu().numpy()
+        err = O.rel_err(got, ref)
+        flops = 8.0 * d.n_beams * d.m_win ** 2 * len(xy)
+        res[name] = {"synthesis_s": dt, "probes_per_s": len(xy) / dt, "contract_ms": cms,
+                     "contract_useful_TFLOP_per_s": flops / (cms * 1e-3) / 1e12, "rel_err_vs_fp64": err}
+        log(f"  {name}: {dt * 1e3:.1f} ms, contract {cms:.1f} ms, rel err {err:.3e}")
+    print(json.dumps({"precision_study": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -178,6 +268,9 @@ def main():
         sys.exit(2)
     if args.serve:
         run_serving(args)
+        return
+    if args.precision_study:
+        precision_study(args)
         return
 
     import numpy as np
@@ -295,6 +388,7 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
+    res["multislice"] = multislice_leg(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle, bounded sample)")
         res["cpu_baseline"] = cpu_baseline(w, d, B, n_probes, args)

@@ -1,0 +1,97 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times, on outputs the FP64 oracle can compute one by one:
+
+* 1024^2 PRISM f = 4 (1245 beams, 50 slices): the whole S-matrix is built on
+  the GPU; sampled layers are compared with the oracle's single-beam build.
+* the same geometry's probe synthesis over the full 128 x 128 scan on a seeded
+  S-matrix operand; sampled probes against the oracle (FP32 and split-BF16).
+* 1024^2 multislice (50 slices): sampled probes of the 64 x 64 scan.
+* 2048^2 PRISM f = 8 (1245 beams, 50 slices): sampled S-matrix layers.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_1706_08563_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def _potentials(P, w):
+    pos, sp = W.atoms_for(w)
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    V = P.prism_project_potential(pos, sp, w.species, g)
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    return g, V, Vref
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_smatrix_sampled_layers(P, cfg):
+    import torch
+    w = W.CONFIGS[cfg]
+    say(f"full S-matrix {w.name}: build on GPU, sampled layers vs oracle")
+    g, V, Vref = _potentials(P, w)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    S = P.prism_build_smatrix(d, V)
+    torch.cuda.synchronize()
+    beams = P.prism_beam_list(d)
+    t = O.transmission(Vref, d.sigma)
+    Pp = O.propagator(w.n, w.cell[0], d.lambda_, w.dz)
+    sample = (0, 311, len(beams) // 2, len(beams) - 1) if cfg == 2 else (0, len(beams) // 2 + 7)
+    for b in sample:
+        ref = O.smatrix_layer(t, Pp, int(beams[b, 0]), int(beams[b, 1]))
+        got = S[b].cpu().numpy().astype(np.complex128)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        say(f"  beam {b} {tuple(beams[b])}: rel err {err:.3e}")
+        assert err <= TOL
+
+
+def test_full_synthesis_sampled_probes(P):
+    import torch
+    w = W.CONFIGS[2]
+    say("full synthesis 1024^2 f=4, 128x128 probes, seeded S operand")
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    rng = np.random.default_rng(202)
+    Sh = W.random_complex((d.n_beams, d.ns, d.ns), rng)
+    S = torch.from_numpy(Sh).cuda()
+    xy = W.scan_positions(w.cell, *w.scan)
+    plan = P.prism_probe_plan_upload(d, xy)
+    pick = np.array([0, 1, 127, 128, 4095, 8192 + 64, 12345, 16383])
+    beams = P.prism_beam_list(d).astype(np.int64)
+    ref = O.prism_outputs(Sh, beams, w.cell[0], w.n, d.lambda_, w.f, xy[pick])
+    for name, prec in (("fp32", P.PRISM_FP32), ("bf16x3", P.PRISM_SPLIT_BF16X3)):
+        out = P.prism_probe_outputs(d, S, plan, prec).cpu().numpy()
+        err = O.rel_err(out[pick], ref)
+        say(f"  {name}: rel err on {len(pick)} sampled probes {err:.3e}")
+        assert err <= TOL
+
+
+def test_full_multislice_sampled_probes(P):
+    w = W.CONFIGS[1]
+    say("full multislice 1024^2, 50 slices, sampled probes of the 64x64 scan")
+    g, V, Vref = _potentials(P, w)
+    xy = W.scan_positions(w.cell, *w.scan)
+    pick = np.array([0, 2080, 4095])
+    out = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=1024).cpu().numpy()
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    ref = O.multislice_outputs(Vref, w.cell[0], w.dz, lam, sig, w.alpha_max, xy[pick])
+    e_all = O.rel_err(out[pick], ref)
+    e_adf = O.rel_err(O.adf_signal(out[pick], 1e-3, 0.04), O.adf_signal(ref, 1e-3, 0.04))
+    say(f"  rel_all {e_all:.3e} rel_adf {e_adf:.3e}")
+    assert e_all <= TOL and e_adf <= TOL
