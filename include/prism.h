@@ -96,6 +96,15 @@ typedef struct prism_smatrix_desc {
     size_t build_ws_bytes;   /* workspace of prism_build_smatrix for min(beam_batch, n_beams) beams per launch */
 } prism_smatrix_desc;
 
+/* Coherent probe aberrations carried by the probe coefficients ("PRISM Probe
+ * Simulations"): exp(-i chi(q)), chi = pi lambda C1 |q|^2 + (pi/2) C3 lambda^3 |q|^4.
+ * C1 (defocus) and C3 (spherical aberration) in A; C1 > 0 equals free
+ * propagation of the probe over C1 before the specimen. */
+typedef struct prism_aberrations {
+    double C1;
+    double C3;
+} prism_aberrations;
+
 /* Probe-synthesis plan (host side of a plan whose tables live in device memory). */
 typedef struct prism_probe_plan {
     int64_t n_probes;
@@ -107,7 +116,8 @@ typedef struct prism_probe_plan {
     double dalpha;           /* bin width (rad) */
     size_t plan_bytes;       /* device bytes of the plan tables */
     size_t ws_bytes;         /* workspace of prism_probe_outputs for all probes at once */
-    size_t off[8];           /* internal: offsets of the tables inside the plan buffer */
+    double C1, C3;           /* aberrations the plan was made with */
+    size_t off[9];           /* internal: offsets of the tables inside the plan buffer */
 } prism_probe_plan;
 
 /* ---- grid ---------------------------------------------------------------- */
@@ -162,9 +172,11 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S,
 /* Plan the synthesis of n_probes probes at probe_xy (host float64 [n][2], A):
  * window centres (nearest S-grid pixel), the (pixel tile, probe) cover lists,
  * and the detector bin tables.  dalpha: bin width (rad); n_bins <= 0 selects
- * ceil(alpha_aa / dalpha).  Fills *plan (sizes) only. */
+ * ceil(alpha_aa / dalpha).  ab: aberrations, NULL for none.  Fills *plan
+ * (sizes) only. */
 int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes,
-                          double dalpha, int32_t n_bins, prism_probe_plan* plan);
+                          double dalpha, int32_t n_bins, const prism_aberrations* ab,
+                          prism_probe_plan* plan);
 
 /* Compute the plan tables and upload them into plan_dev (device, plan->plan_bytes).
  * Uploads host tables (waits for the copy on `stream`). */
@@ -174,13 +186,23 @@ int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
 /* out[p][bin] (device float32 [n_probes][n_bins]) = sum over the bin's window
  * pixels of |FFT_M(psi_p)|^2 / M^4, where
  * psi_p[v][u] = sum_b c_b(p) S_b[(cy - M/2 + v) mod ns][(cx - M/2 + u) mod ns],
- * c_b(p) = |B_f|^(-1/2) exp(-2 pi i (kx_b x_p + ky_b y_p)/L).
+ * c_b(p) = |B_f|^(-1/2) exp(-2 pi i (kx_b x_p + ky_b y_p)/L) exp(-i chi(q_b)).
  * precision: PRISM_FP32, PRISM_SPLIT_BF16X3 or PRISM_BF16.  Fully asynchronous.
  * Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE (ws_bytes < plan->ws_bytes), PRISM_E_DEVICE. */
 int prism_probe_outputs(const prism_smatrix_desc* d, const void* S,
                         const prism_probe_plan* plan, const void* plan_dev,
                         int32_t precision, float* out,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* 4D output (Fig. 1e/k, "the entire probe diffraction pattern"):
+ * out4d[p][ky][kx] (device float32 [n_probes][m_win][m_win], FFT order on the
+ * window's Fourier grid, pitch f/L) = |FFT_M(psi_p)|^2 / M^4, psi_p as in
+ * prism_probe_outputs.  Same workspace as prism_probe_outputs.  Fully
+ * asynchronous.  Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
+int prism_probe_diffraction(const prism_smatrix_desc* d, const void* S,
+                            const prism_probe_plan* plan, const void* plan_dev,
+                            int32_t precision, float* out4d,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* One request's probe synthesis inside a batched call (all pointers borrowed
  * for the call; device pointers as in prism_probe_outputs). */
@@ -189,7 +211,11 @@ typedef struct prism_probe_job {
     const void* S;                    /* device complex64 [n_beams][ns][ns] */
     const prism_probe_plan* plan;     /* host */
     const void* plan_dev;             /* device plan tables */
-    float* out;                       /* device float32 [n_probes][n_bins] */
+    float* out;                       /* device float32 [n_probes][n_bins] (3D output), or NULL */
+    float* diffraction;               /* device float32 [n_probes][m_win][m_win] (4D output), or NULL */
+    float out_scale;                  /* out = out_scale * bin sums ...                    */
+    int32_t accumulate;               /* ... + the previous contents of out when 1 (e.g.
+                                         averaging frozen-phonon configurations); 0 or 1 */
 } prism_probe_job;
 
 /* Workspace bytes of prism_probe_outputs_batched for these jobs. */
@@ -212,15 +238,16 @@ int prism_probe_outputs_batched(const prism_probe_job* jobs, int32_t n_jobs, int
 int multislice_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes, size_t* bytes);
 
 /* out[p][bin] (device float32 [n_probes][n_bins]): hard-aperture probe
- * (lambda |q| <= alpha_max) with coefficients |B_1|^(-1/2) exp(-2 pi i q.r_p),
+ * (lambda |q| <= alpha_max) with coefficients |B_1|^(-1/2) exp(-2 pi i q.r_p)
+ * exp(-i chi(q)) (ab: aberrations, NULL for none),
  * transmitted and propagated through every slice (Eqs. 1-2), then
  * |Psi(q)|^2 / n^4 summed over annular bins of width dalpha up to alpha_aa.
  * probe_xy: host float64 [n_probes][2].  V: device float32 [n_slices][n][n].
  * The probes are processed `batch` at a time inside ws.  Uploads host tables.
  * Errors: PRISM_E_INVAL, PRISM_E_UNSUPPORTED, PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
-int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const float* V,
-                       const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins,
-                       int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream);
+int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                       const float* V, const double* probe_xy, int64_t n_probes, double dalpha,
+                       int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- detector geometry ------------------------------------------------------ */
 

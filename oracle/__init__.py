@@ -29,9 +29,9 @@ from .stem import (  # noqa: F401
     slice_index, projected_potential,
     transmission, propagator,
     alpha_aa, default_n_bins, bin_map,
-    beam_set, probe_coefficients,
+    beam_set, probe_coefficients, aberration_phase,
     multislice_outputs, multislice_exit_spectrum,
     smatrix_layer, build_smatrix,
-    window_centre, probe_window, prism_outputs,
+    window_centre, probe_window, prism_outputs, prism_diffraction, frozen_phonon_prism,
     rel_err, adf_signal,
 )

@@ -19,7 +19,9 @@ leaves open:
 * Step order: in every slice, transmit (Eq. 1) then propagate (Eq. 2),
   including after the last slice.
 * Probe: hard aperture (Airy disk, Fig. 1c), lambda |q| <= alpha_max inclusive,
-  no aberrations, coefficients normalised so that sum |c|^2 = 1.
+  coefficients normalised so that sum |c|^2 = 1; optional coherent aberrations
+  exp(-i chi), chi = pi lam C1 q^2 + (pi/2) C3 lam^3 q^4 (defocus C1 > 0 is
+  free propagation over C1 with the Eq. (2) propagator).
 * PRISM window: side M = (n/2)/f pixels of the S-matrix grid (L/f in A),
   centred on the S-grid pixel nearest the probe (round half up), starting at
   centre - M/2, periodic.
@@ -207,30 +209,46 @@ def beam_set(n: int, L: float, lam: float, alpha_max: float, f: int) -> np.ndarr
     return np.array(out, dtype=np.int64).reshape(-1, 2)
 
 
-def probe_coefficients(beams, L: float, xy) -> np.ndarray:
-    """c[p][b] = |B|^(-1/2) exp(-2 pi i (kx x_p + ky y_p) / L).
+def aberration_phase(beams, L: float, lam: float, C1: float = 0.0, C3: float = 0.0) -> np.ndarray:
+    """chi(q) = pi lam C1 |q|^2 + (pi/2) C3 lam^3 |q|^4 for each beam (rad).
+
+    Coherent wave aberrations carried by the probe coefficients ("PRISM Probe
+    Simulations": defocus C1 and spherical aberration C3, both in A).  With
+    the propagator exp(-i pi lam |q|^2 dz) of Eq. (2), exp(-i chi) at C3 = 0
+    is free propagation over C1.
+    """
+    q2 = (beams[:, 0].astype(np.float64) / L) ** 2 + (beams[:, 1].astype(np.float64) / L) ** 2
+    return math.pi * lam * C1 * q2 + 0.5 * math.pi * C3 * lam ** 3 * q2 * q2
+
+
+def probe_coefficients(beams, L: float, xy, lam: float = 0.0, C1: float = 0.0, C3: float = 0.0) -> np.ndarray:
+    """c[p][b] = |B|^(-1/2) exp(-2 pi i (kx x_p + ky y_p) / L) exp(-i chi(q_b)).
 
     Fourier phase shifts that translate each plane wave so the summed probe is
-    centred at (x_p, y_p) ("PRISM Probe Simulations").
+    centred at (x_p, y_p), times the aberration phase ("PRISM Probe
+    Simulations").
     """
     xy = np.atleast_2d(np.asarray(xy, dtype=np.float64))
     kx = beams[:, 0].astype(np.float64)
     ky = beams[:, 1].astype(np.float64)
     arg = (xy[:, 0:1] * kx[None, :] + xy[:, 1:2] * ky[None, :]) / L
-    return np.exp(-2j * math.pi * arg) / math.sqrt(len(beams))
+    c = np.exp(-2j * math.pi * arg) / math.sqrt(len(beams))
+    if C1 or C3:
+        c = c * np.exp(-1j * aberration_phase(beams, L, lam, C1, C3))[None, :]
+    return c
 
 
 # ---------------------------------------------------------------------------
 # Multislice (Fig. 1c-e; "Multislice Probe Simulations").
 # ---------------------------------------------------------------------------
 def multislice_exit_spectrum(V, L: float, dz: float, lam: float, sigma: float,
-                             alpha_max: float, xy):
+                             alpha_max: float, xy, C1: float = 0.0, C3: float = 0.0):
     """Psi(k) after the last slice for one probe at xy (Fourier space, FFT order)."""
     S, n, _ = V.shape
     t = transmission(V, sigma)
     P = propagator(n, L, lam, dz)
     ap = beam_set(n, L, lam, alpha_max, 1)
-    c = probe_coefficients(ap, L, xy)[0]
+    c = probe_coefficients(ap, L, xy, lam, C1, C3)[0]
     Psi0 = np.zeros((n, n), dtype=np.complex128)
     Psi0[ap[:, 1] % n, ap[:, 0] % n] = c
     psi = n * n * ifft2(Psi0)
@@ -244,7 +262,8 @@ def multislice_exit_spectrum(V, L: float, dz: float, lam: float, sigma: float,
 
 
 def multislice_outputs(V, L: float, dz: float, lam: float, sigma: float, alpha_max: float,
-                       probe_xy, dalpha: float = 1e-3, n_bins: int | None = None):
+                       probe_xy, dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0,
+                       C3: float = 0.0):
     """D[p][bin] = sum over bin of |Psi_exit|^2 / n^4 for each probe (3D output)."""
     S, n, _ = V.shape
     if n_bins is None:
@@ -253,7 +272,7 @@ def multislice_outputs(V, L: float, dz: float, lam: float, sigma: float, alpha_m
     probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
     D = np.zeros((len(probe_xy), n_bins))
     for p in range(len(probe_xy)):
-        Psi = multislice_exit_spectrum(V, L, dz, lam, sigma, alpha_max, probe_xy[p])
+        Psi = multislice_exit_spectrum(V, L, dz, lam, sigma, alpha_max, probe_xy[p], C1, C3)
         D[p] = detect(np.abs(Psi) ** 2 / float(n) ** 4, bmap, n_bins)
     return D
 
@@ -304,7 +323,7 @@ def probe_window(Smat, c, cx: int, cy: int, M: int):
 
 
 def prism_outputs(Smat, beams, L: float, n: int, lam: float, f: int, probe_xy,
-                  dalpha: float = 1e-3, n_bins: int | None = None):
+                  dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0, C3: float = 0.0):
     """D[p][bin] for each probe from a compact S-matrix (3D output)."""
     Ns = n // 2
     M = Ns // f
@@ -313,7 +332,7 @@ def prism_outputs(Smat, beams, L: float, n: int, lam: float, f: int, probe_xy,
         n_bins = default_n_bins(lam, n, L, dalpha)
     bmap = bin_map(lam, M, Lw, alpha_aa(lam, n, L), dalpha, n_bins)
     probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
-    C = probe_coefficients(beams, L, probe_xy)
+    C = probe_coefficients(beams, L, probe_xy, lam, C1, C3)
     D = np.zeros((len(probe_xy), n_bins))
     for p in range(len(probe_xy)):
         cx = window_centre(probe_xy[p, 0], L, n)
@@ -322,6 +341,39 @@ def prism_outputs(Smat, beams, L: float, n: int, lam: float, f: int, probe_xy,
         I = np.abs(fft2(w)) ** 2 / float(M) ** 4
         D[p] = detect(I, bmap, n_bins)
     return D
+
+
+def prism_diffraction(Smat, beams, L: float, n: int, lam: float, f: int, probe_xy,
+                      C1: float = 0.0, C3: float = 0.0):
+    """I[p][ky][kx] = |FFT_M(psi_p)|^2 / M^4 on the window's Fourier grid (FFT
+    order): the entire probe diffraction pattern of each probe, the 4D output
+    of Fig. 1e/k."""
+    Ns = n // 2
+    M = Ns // f
+    probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
+    C = probe_coefficients(beams, L, probe_xy, lam, C1, C3)
+    out = np.zeros((len(probe_xy), M, M))
+    for p in range(len(probe_xy)):
+        cx = window_centre(probe_xy[p, 0], L, n)
+        cy = window_centre(probe_xy[p, 1], L, n)
+        w = probe_window(Smat, C[p], cx, cy, M)
+        out[p] = np.abs(fft2(w)) ** 2 / float(M) ** 4
+    return out
+
+
+def frozen_phonon_prism(configs, species_idx, species, cell, dz: float, n: int, E0: float, alpha_max: float,
+                        f: int, probe_xy, C1: float = 0.0, C3: float = 0.0):
+    """Mean over thermal configurations of the PRISM 3D output, each
+    configuration simulated in full (frozen-phonon averaging)."""
+    lam, sig = wavelength(E0), interaction_constant(E0)
+    L = float(cell[0])
+    beams = beam_set(n, L, lam, alpha_max, f)
+    acc = None
+    for pos in configs:
+        V = projected_potential(pos, species_idx, species, cell, dz, n)
+        D = prism_outputs(build_smatrix(V, L, dz, lam, sig, beams), beams, L, n, lam, f, probe_xy, C1=C1, C3=C3)
+        acc = D if acc is None else acc + D
+    return acc / len(configs)
 
 
 # ---------------------------------------------------------------------------

@@ -15,5 +15,5 @@ from .api import (  # noqa: F401
     prism_project_potential, prism_build_smatrix, prism_probe_plan_init, prism_probe_plan_upload,
     prism_probe_outputs, multislice_outputs, multislice_workspace, ProbePlan,
     prism_timing_enable, prism_timing_reset, prism_timing_read,
-    prism_probe_batch_workspace, prism_probe_outputs_batched,
+    prism_probe_batch_workspace, prism_probe_outputs_batched, prism_probe_diffraction,
 )

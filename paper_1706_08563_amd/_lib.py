@@ -42,15 +42,21 @@ class prism_smatrix_desc(ctypes.Structure):
                 ("smatrix_bytes", c_size_t), ("build_ws_bytes", c_size_t)]
 
 
+class prism_aberrations(ctypes.Structure):
+    _fields_ = [("C1", c_double), ("C3", c_double)]
+
+
 class prism_probe_plan(ctypes.Structure):
     _fields_ = [("n_probes", c_int64), ("n_bins", c_int32), ("n_tiles", c_int32), ("n_entries", c_int64),
                 ("max_per_tile", c_int32), ("n_binned", c_int32), ("dalpha", c_double),
-                ("plan_bytes", c_size_t), ("ws_bytes", c_size_t), ("off", c_size_t * 8)]
+                ("plan_bytes", c_size_t), ("ws_bytes", c_size_t), ("C1", c_double), ("C3", c_double),
+                ("off", c_size_t * 9)]
 
 
 class prism_probe_job(ctypes.Structure):
     _fields_ = [("desc", POINTER(prism_smatrix_desc)), ("S", c_void_p), ("plan", POINTER(prism_probe_plan)),
-                ("plan_dev", c_void_p), ("out", c_void_p)]
+                ("plan_dev", c_void_p), ("out", c_void_p), ("diffraction", c_void_p), ("out_scale", ctypes.c_float),
+                ("accumulate", c_int32)]
 
 
 class PrismError(RuntimeError):
@@ -70,17 +76,19 @@ _SIGNATURES = {
     "prism_build_smatrix": ([POINTER(prism_smatrix_desc), c_void_p, c_void_p, c_void_p, c_size_t, c_void_p],
                             c_int32),
     "prism_probe_plan_init": ([POINTER(prism_smatrix_desc), c_void_p, c_int64, c_double, c_int32,
-                               POINTER(prism_probe_plan)], c_int32),
+                               POINTER(prism_aberrations), POINTER(prism_probe_plan)], c_int32),
     "prism_probe_plan_upload": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p,
                                  c_void_p], c_int32),
     "prism_probe_outputs": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p, c_int32,
                              c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
+    "prism_probe_diffraction": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p, c_int32,
+                                 c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "prism_probe_batch_workspace": ([POINTER(prism_probe_job), c_int32, POINTER(c_size_t)], c_int32),
     "prism_probe_outputs_batched": ([POINTER(prism_probe_job), c_int32, c_int32, c_void_p, c_size_t, c_void_p],
                                     c_int32),
     "multislice_workspace": ([POINTER(prism_grid), c_int32, c_int64, POINTER(c_size_t)], c_int32),
-    "multislice_outputs": ([POINTER(prism_grid), c_double, c_double, c_void_p, c_void_p, c_int64, c_double, c_int32,
-                            c_int32, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
+    "multislice_outputs": ([POINTER(prism_grid), c_double, c_double, POINTER(prism_aberrations), c_void_p, c_void_p,
+                            c_int64, c_double, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "prism_detector_bin_map": ([c_double, c_double, c_double, c_double, c_int32, c_int32, c_void_p], c_int32),
     "prism_timing_enable": ([c_int32], c_int32),
     "prism_timing_reset": ([], c_int32),

@@ -12,7 +12,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from ._lib import (lib, check, prism_atom, prism_species, prism_grid, prism_smatrix_desc, prism_probe_plan,
-                   prism_probe_job, PRISM_FP32)
+                   prism_probe_job, prism_aberrations, PRISM_FP32)
 
 
 def _torch():
@@ -112,18 +112,27 @@ class ProbePlan:
     xy: np.ndarray       # host positions the plan was made for
 
 
-def prism_probe_plan_init(d: prism_smatrix_desc, xy, dalpha: float = 1e-3, n_bins: int = 0) -> prism_probe_plan:
+def _aberrations(C1, C3):
+    if not C1 and not C3:
+        return None
+    ab = prism_aberrations()
+    ab.C1, ab.C3 = float(C1), float(C3)
+    return ctypes.byref(ab)
+
+
+def prism_probe_plan_init(d: prism_smatrix_desc, xy, dalpha: float = 1e-3, n_bins: int = 0, C1: float = 0.0,
+                          C3: float = 0.0) -> prism_probe_plan:
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
     p = prism_probe_plan()
     check(lib.prism_probe_plan_init(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha),
-                                    int(n_bins), ctypes.byref(p)))
+                                    int(n_bins), _aberrations(C1, C3), ctypes.byref(p)))
     return p
 
 
 def prism_probe_plan_upload(d: prism_smatrix_desc, xy, dalpha: float = 1e-3, n_bins: int = 0,
-                            device=None) -> ProbePlan:
+                            device=None, C1: float = 0.0, C3: float = 0.0) -> ProbePlan:
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
-    p = prism_probe_plan_init(d, xy, dalpha, n_bins)
+    p = prism_probe_plan_init(d, xy, dalpha, n_bins, C1, C3)
     dev = _workspace(p.plan_bytes, device)
     check(lib.prism_probe_plan_upload(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p),
                                       _dev(dev), _stream()))
@@ -143,19 +152,38 @@ def prism_probe_outputs(d: prism_smatrix_desc, S, plan: ProbePlan, precision: in
     return out
 
 
+def prism_probe_diffraction(d: prism_smatrix_desc, S, plan: ProbePlan, precision: int = PRISM_FP32, ws=None,
+                            out=None):
+    """out [n_probes, m, m] float32 on the device: |FFT_M(psi_p)|^2 / M^4 (4D output)."""
+    torch = _torch()
+    p = plan.plan
+    if out is None:
+        out = torch.empty((p.n_probes, d.m_win, d.m_win), dtype=torch.float32, device=S.device)
+    if ws is None:
+        ws = _workspace(p.ws_bytes, S.device)
+    check(lib.prism_probe_diffraction(ctypes.byref(d), _dev(S), ctypes.byref(p), _dev(plan.dev), int(precision),
+                                      _dev(out), _dev(ws), ws.numel(), _stream()))
+    return out
+
+
 def _jobs(items):
     arr = (prism_probe_job * max(len(items), 1))()
-    for k, (d, S, plan, out) in enumerate(items):
+    for k, it in enumerate(items):
+        d, S, plan, out = it[:4]
+        diff = it[4] if len(it) > 4 else None
         arr[k].desc = ctypes.pointer(d)
         arr[k].S = S.data_ptr()
         arr[k].plan = ctypes.pointer(plan.plan)
         arr[k].plan_dev = plan.dev.data_ptr()
-        arr[k].out = out.data_ptr()
+        arr[k].out = out.data_ptr() if out is not None else None
+        arr[k].diffraction = diff.data_ptr() if diff is not None else None
+        arr[k].out_scale = float(it[5]) if len(it) > 5 else 1.0
+        arr[k].accumulate = int(it[6]) if len(it) > 6 else 0
     return arr
 
 
 def prism_probe_batch_workspace(items) -> int:
-    """items: list of (desc, S, ProbePlan, out) tuples."""
+    """items: list of (desc, S, ProbePlan, out[, diffraction[, out_scale[, accumulate]]]) tuples."""
     need = ctypes.c_size_t()
     check(lib.prism_probe_batch_workspace(_jobs(items), len(items), ctypes.byref(need)))
     return need.value
@@ -178,7 +206,7 @@ def multislice_workspace(grid: prism_grid, batch: int, n_probes: int) -> int:
 
 
 def multislice_outputs(grid: prism_grid, E0: float, alpha_max: float, V, xy, dalpha: float = 1e-3,
-                       n_bins: int = 0, batch: int = 64, ws=None, out=None):
+                       n_bins: int = 0, batch: int = 64, ws=None, out=None, C1: float = 0.0, C3: float = 0.0):
     """out [n_probes, n_bins] float32 on the device."""
     torch = _torch()
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
@@ -190,7 +218,7 @@ def multislice_outputs(grid: prism_grid, E0: float, alpha_max: float, V, xy, dal
         ws = _workspace(multislice_workspace(grid, batch, len(xy)), V.device)
     if out is None:
         out = torch.empty((len(xy), n_bins), dtype=torch.float32, device=V.device)
-    check(lib.multislice_outputs(ctypes.byref(grid), float(E0), float(alpha_max), _dev(V),
+    check(lib.multislice_outputs(ctypes.byref(grid), float(E0), float(alpha_max), _aberrations(C1, C3), _dev(V),
                                  xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha), int(n_bins), int(batch),
                                  _dev(out), _dev(ws), ws.numel(), _stream()))
     return out

@@ -129,6 +129,17 @@ inline int centre_of(double x, double L, int n) {
 
 int default_bins(double a_aa, double dalpha) { return (int)std::ceil(a_aa / dalpha); }
 
+// exp(-i chi(q)), chi = pi lam C1 q^2 + (pi/2) C3 lam^3 q^4, q = k/L: the phase
+// is formed and reduced mod 2 pi in FP64, the factor stored in FP32.
+float2 aberration_factor(int kx, int ky, double L, double lam, double C1, double C3) {
+    const double q2 = ((double)kx / L) * ((double)kx / L) + ((double)ky / L) * ((double)ky / L);
+    // chi / pi, reduced to (-1, 1]
+    double t = lam * C1 * q2 + 0.5 * C3 * lam * lam * lam * q2 * q2;
+    t -= 2.0 * std::nearbyint(t / 2.0);
+    const double ph = -kPi * t;
+    return make_float2((float)std::cos(ph), (float)std::sin(ph));
+}
+
 // ----------------------------------------------------- workspace carving --
 struct Carve {
     char* base;
@@ -226,6 +237,7 @@ struct ProbeHost {
     std::vector<int> tile_start, tile_probes, perm, bin_start;
     std::vector<float2> tw_m;
     std::vector<int2> beams;
+    std::vector<float2> aberr;      // per beam, empty when there are no aberrations
 };
 
 // Detector tables: pixels (index ky_i * m + kx_i of an m x m FFT-order grid)
@@ -249,7 +261,7 @@ void bin_tables(double lam, double Lw, double a_aa, double dalpha, int n_bins, i
 }
 
 int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, double dalpha, int n_bins,
-               ProbeHost& h, int& max_per_tile) {
+               double C1, double C3, ProbeHost& h, int& max_per_tile) {
     const int n = d->grid.n, ns = d->ns, M = d->m_win;
     const double L = d->grid.cell[0];
     const int ntx = ns / 16, n_tiles = ntx * ntx;
@@ -294,6 +306,12 @@ int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, 
     bin_tables(d->lambda, L / d->f, d->alpha_aa, dalpha, n_bins, M, h.perm, h.bin_start);
     h.tw_m = twiddle_table(M);
     h.beams = beam_list(n, L, d->lambda, d->alpha_max, d->f);
+    h.aberr.clear();
+    if (C1 != 0.0 || C3 != 0.0) {
+        h.aberr.resize(h.beams.size());
+        for (size_t b = 0; b < h.beams.size(); ++b)
+            h.aberr[b] = aberration_factor(h.beams[b].x, h.beams[b].y, L, d->lambda, C1, C3);
+    }
     return PRISM_OK;
 }
 
@@ -527,15 +545,17 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
 
 // -------------------------------------------------------- probe outputs --
 int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes, double dalpha,
-                          int32_t n_bins, prism_probe_plan* plan) {
+                          int32_t n_bins, const prism_aberrations* ab, prism_probe_plan* plan) {
     int rc = check_desc(d);
     if (rc) return rc;
     if (!plan || (n_probes > 0 && !probe_xy) || n_probes < 0 || n_probes > (1 << 30) || !(dalpha > 0))
         return fail(PRISM_E_INVAL, "probe plan: invalid argument");
+    const double C1 = ab ? ab->C1 : 0.0, C3 = ab ? ab->C3 : 0.0;
+    if (!std::isfinite(C1) || !std::isfinite(C3)) return fail(PRISM_E_INVAL, "probe plan: non-finite aberrations");
     if (n_bins <= 0) n_bins = default_bins(d->alpha_aa, dalpha);
     ProbeHost h;
     int maxpt = 0;
-    rc = probe_host(d, probe_xy, n_probes, dalpha, n_bins, h, maxpt);
+    rc = probe_host(d, probe_xy, n_probes, dalpha, n_bins, C1, C3, h, maxpt);
     if (rc) return rc;
     prism_probe_plan p{};
     p.n_probes = n_probes;
@@ -545,6 +565,8 @@ int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, i
     p.max_per_tile = maxpt;
     p.n_binned = (int32_t)h.perm.size();
     p.dalpha = dalpha;
+    p.C1 = C1;
+    p.C3 = C3;
     Carve c(nullptr);
     const size_t P = (size_t)std::max<int64_t>(n_probes, 1);
     p.off[0] = (size_t)c.take<double2>(P);
@@ -555,6 +577,7 @@ int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, i
     p.off[5] = (size_t)c.take<int>(h.bin_start.size());
     p.off[6] = (size_t)c.take<float2>(h.tw_m.size());
     p.off[7] = (size_t)c.take<int2>(h.beams.size());
+    p.off[8] = h.aberr.empty() ? 0 : (size_t)c.take<float2>(h.aberr.size());
     p.plan_bytes = c.off + 256;
     Carve w(nullptr);
     synth_job_bytes(d, &p, w);
@@ -570,7 +593,7 @@ int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
     if (!plan || !plan_dev) return fail(PRISM_E_INVAL, "probe plan upload: NULL argument");
     ProbeHost h;
     int maxpt = 0;
-    rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, h, maxpt);
+    rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, plan->C1, plan->C3, h, maxpt);
     if (rc) return rc;
     if ((int64_t)h.tile_probes.size() != plan->n_entries || (int)h.perm.size() != plan->n_binned)
         return fail(PRISM_E_INVAL, "probe plan upload: plan does not match these probes");
@@ -586,6 +609,7 @@ int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
     put(plan->off[5], h.bin_start.data(), h.bin_start.size() * sizeof(int));
     put(plan->off[6], h.tw_m.data(), h.tw_m.size() * sizeof(float2));
     put(plan->off[7], h.beams.data(), h.beams.size() * sizeof(int2));
+    if (!h.aberr.empty()) put(plan->off[8], h.aberr.data(), h.aberr.size() * sizeof(float2));
     return upload(plan_dev, blob, as_stream(stream));
 }
 
@@ -598,8 +622,10 @@ static int synth_validate(const prism_probe_job* jobs, int n_jobs, int precision
         const prism_probe_job& jb = jobs[k];
         int rc = check_desc(jb.desc);
         if (rc) return rc;
-        if (!jb.S || !jb.plan || !jb.plan_dev || (!jb.out && jb.plan->n_probes > 0))
+        if (!jb.S || !jb.plan || !jb.plan_dev || (!jb.out && !jb.diffraction && jb.plan->n_probes > 0))
             return fail(PRISM_E_INVAL, "probe outputs: job %d has a NULL pointer", k);
+        if (!std::isfinite(jb.out_scale) || (jb.accumulate != 0 && jb.accumulate != 1))
+            return fail(PRISM_E_INVAL, "probe outputs: job %d: bad out_scale or accumulate", k);
         synth_job_bytes(jb.desc, jb.plan, c);
     }
     *need = c.off + 256;
@@ -632,15 +658,17 @@ static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, voi
         auto bstart = reinterpret_cast<const int*>(pb + plan->off[5]);
         auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
         auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
+        auto aberr = (plan->C1 != 0.0 || plan->C3 != 0.0) ? reinterpret_cast<const float2*>(pb + plan->off[8]) : nullptr;
         HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
-            return launch_coefficients(C, xy, beams, P, B, 1.0 / d->grid.cell[0], (float)(1.0 / std::sqrt((double)B)),
-                                       st);
+            return launch_coefficients(C, xy, beams, aberr, P, B, 1.0 / d->grid.cell[0],
+                                       (float)(1.0 / std::sqrt((double)B)), st);
         }));
         ca.push_back(ContractArgs{C, static_cast<const float2*>(jb.S), win, tstart, tprobes, corner, plan->n_tiles,
                                   plan->max_per_tile, B, d->ns, M});
         int lg = 0;
         while ((1 << lg) < M) ++lg;
-        wa[lg].push_back(WindowArgs{win, inten, jb.out, perm, bstart, tw_m, P, plan->n_bins});
+        wa[lg].push_back(WindowArgs{win, inten, jb.out, jb.diffraction, perm, bstart, tw_m, P, plan->n_bins,
+                                    jb.out_scale, jb.accumulate});
     }
     if (!ca.empty())
         HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] { return launch_contract_batch(precision, ca.data(), (int)ca.size(), st); }));
@@ -653,12 +681,26 @@ static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, voi
 int prism_probe_outputs(const prism_smatrix_desc* d, const void* S, const prism_probe_plan* plan,
                         const void* plan_dev, int32_t precision, float* out, void* ws, size_t ws_bytes,
                         void* stream) {
-    prism_probe_job jb{d, S, plan, plan_dev, out};
+    prism_probe_job jb{d, S, plan, plan_dev, out, nullptr, 1.0f, 0};
     size_t need = 0;
     int rc = synth_validate(&jb, 1, precision, &need);
     if (rc) return rc;
     if (!ws || ws_bytes < plan->ws_bytes)
         return fail(PRISM_E_WORKSPACE, "probe outputs: workspace %zu < %zu bytes", ws_bytes, plan->ws_bytes);
+    if (plan->n_probes == 0) return PRISM_OK;
+    return synth_run(&jb, 1, precision, ws, as_stream(stream));
+}
+
+int prism_probe_diffraction(const prism_smatrix_desc* d, const void* S, const prism_probe_plan* plan,
+                            const void* plan_dev, int32_t precision, float* out4d, void* ws, size_t ws_bytes,
+                            void* stream) {
+    prism_probe_job jb{d, S, plan, plan_dev, nullptr, out4d, 1.0f, 0};
+    size_t need = 0;
+    int rc = synth_validate(&jb, 1, precision, &need);
+    if (rc) return rc;
+    if (!out4d) return fail(PRISM_E_INVAL, "probe diffraction: NULL output");
+    if (!ws || ws_bytes < plan->ws_bytes)
+        return fail(PRISM_E_WORKSPACE, "probe diffraction: workspace %zu < %zu bytes", ws_bytes, plan->ws_bytes);
     if (plan->n_probes == 0) return PRISM_OK;
     return synth_run(&jb, 1, precision, ws, as_stream(stream));
 }
@@ -681,8 +723,9 @@ int prism_probe_outputs_batched(const prism_probe_job* jobs, int32_t n_jobs, int
 // ------------------------------------------------------------ multislice --
 static void multislice_carve(Carve& c, int n, int nsl, int64_t n_probes, int batch, int n_bins, size_t n_binned,
                              PropDev& pd, int*& kymax, int*& perm, int*& bstart, double2*& xy, float2*& T,
-                             float2*& W, float*& I) {
+                             float2*& W, float*& I, float2*& aberr) {
     pd = carve_prop(c, n);
+    aberr = c.take<float2>((size_t)(n / 2) * (n / 2));
     kymax = c.take<int>(n / 2);
     perm = c.take<int>(std::max<size_t>(n_binned, 1));
     bstart = c.take<int>(n_bins + 1);
@@ -701,17 +744,18 @@ int multislice_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes
     PropDev pd;
     int *a, *b, *e;
     double2* xy;
-    float2 *T, *W;
+    float2 *T, *W, *ab;
     float* I;
     // bins can cover at most the (n/2)^2 band pixels
-    multislice_carve(c, n, grid->n_slices, n_probes, batch, 4096, (size_t)(n / 2) * (n / 2), pd, a, b, e, xy, T, W, I);
+    multislice_carve(c, n, grid->n_slices, n_probes, batch, 4096, (size_t)(n / 2) * (n / 2), pd, a, b, e, xy, T, W, I,
+                     ab);
     *bytes = c.off + 256;
     return PRISM_OK;
 }
 
-int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const float* V, const double* probe_xy,
-                       int64_t n_probes, double dalpha, int32_t n_bins, int32_t batch, float* out, void* ws,
-                       size_t ws_bytes, void* stream) {
+int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                       const float* V, const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins,
+                       int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_grid(grid);
     if (rc) return rc;
     if (!V || !out || (n_probes > 0 && !probe_xy) || n_probes < 0 || batch < 1 || !(E0 > 0) || !(alpha_max > 0) ||
@@ -739,6 +783,16 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
         if (m >= 0) n_ap += 2 * m + 1;
     }
     if (n_ap == 0) return fail(PRISM_E_INVAL, "multislice: empty aperture");
+    // aberration factor of every band pixel [j][j'] (kx from j, ky from j')
+    const double C1 = ab ? ab->C1 : 0.0, C3 = ab ? ab->C3 : 0.0;
+    if (!std::isfinite(C1) || !std::isfinite(C3)) return fail(PRISM_E_INVAL, "multislice: non-finite aberrations");
+    std::vector<float2> aberr;
+    if (C1 != 0.0 || C3 != 0.0) {
+        aberr.resize((size_t)Lh * Lh);
+        for (int j = 0; j < Lh; ++j)
+            for (int jp = 0; jp < Lh; ++jp)
+                aberr[(size_t)j * Lh + jp] = aberration_factor(band_k(j, n), band_k(jp, n), L, lam, C1, C3);
+    }
     // bins over band pixels, index j * (n/2) + j' (kx from j, ky from j')
     std::vector<int> cnt(n_bins + 1, 0), bins((size_t)Lh * Lh);
     for (int j = 0; j < Lh; ++j)
@@ -765,9 +819,10 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
     PropDev pd;
     int *d_kymax, *d_perm, *d_bstart;
     double2* d_xy;
-    float2 *T, *W;
+    float2 *T, *W, *d_aberr;
     float* I;
-    multislice_carve(c, n, nsl, n_probes, batch, n_bins, perm.size(), pd, d_kymax, d_perm, d_bstart, d_xy, T, W, I);
+    multislice_carve(c, n, nsl, n_probes, batch, n_bins, perm.size(), pd, d_kymax, d_perm, d_bstart, d_xy, T, W, I,
+                     d_aberr);
     PropHost ph = prop_tables(n, L, lam, grid->dz);
     std::vector<char> blob;
     stage(blob, ws, pd.tw_half, ph.tw_half);
@@ -778,6 +833,7 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
     stage(blob, ws, d_perm, perm);
     stage(blob, ws, d_bstart, bstart);
     stage(blob, ws, d_xy, xy);
+    if (!aberr.empty()) stage(blob, ws, d_aberr, aberr);
     hipStream_t st = as_stream(stream);
     rc = upload(ws, blob, st);
     if (rc) return rc;
@@ -787,7 +843,8 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
     for (int64_t p0 = 0; p0 < n_probes; p0 += batch) {
         const int nb = (int)std::min<int64_t>(batch, n_probes - p0);
         HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
-            return launch_pass_b(n, PASSB_INIT, W, tb, nullptr, nullptr, d_kymax, d_xy + p0, 1.0 / L, amp, nb, st);
+            return launch_pass_b(n, PASSB_INIT, W, tb, aberr.empty() ? nullptr : d_aberr, nullptr, d_kymax, d_xy + p0,
+                                 1.0 / L, amp, nb, st);
         }));
         for (int s = 0; s < nsl; ++s) {
             HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, W, T + (size_t)s * n * n, tb, nullptr, false, nb, st); }));

@@ -34,9 +34,10 @@ hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb
                          bool first_pw, int n_items, hipStream_t st);
 
 // Column pass (see PassBMode).  inten: band intensities [item][j][j'] for
-// PASSB_LAST_I; out_half: [item][j][my] for PASSB_LAST_S.  For PASSB_INIT the
-// spectrum is the aperture: |ky| <= ky_max[j], coefficient amp e^{-2 pi i (kx x + ky y)/L}.
-hipError_t launch_pass_b(int n, int mode, float2* W, const PropTables& tb, float2* out_half, float* inten,
+// PASSB_LAST_I.  For PASSB_INIT the spectrum is the aperture: |ky| <= ky_max[j],
+// coefficient amp e^{-2 pi i (kx x + ky y)/L} times aberr[j][j'] when `aux`
+// (the aberration table, complex [n/2][n/2]) is not null.
+hipError_t launch_pass_b(int n, int mode, float2* W, const PropTables& tb, const float2* aux, float* inten,
                          const int* ky_max, const double2* probe_xy, double inv_L, float amp, int n_items,
                          hipStream_t st);
 
@@ -51,9 +52,10 @@ hipError_t launch_potential(float* V, int n, int n_slices, double L, const PotAt
                             const int* slice_start, const PotSpecies* species, float rc_max, hipStream_t st);
 
 // ---- probe synthesis ----------------------------------------------------------
-// C[p][b] = amp * exp(-2 pi i (kx_b x_p + ky_b y_p) / L) (FP64 argument, range reduced).
-hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, int n_probes, int n_beams,
-                               double inv_L, float amp, hipStream_t st);
+// C[p][b] = amp * exp(-2 pi i (kx_b x_p + ky_b y_p) / L) (FP64 argument, range
+// reduced), times aberr[b] when aberr is not null.
+hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, const float2* aberr, int n_probes,
+                               int n_beams, double inv_L, float amp, hipStream_t st);
 
 // Windowed contraction of one probe set: win[p][v][u] = sum_b C[p][b] S[b][pix].
 struct ContractArgs {
@@ -74,17 +76,21 @@ hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_
 struct WindowArgs {
     float2* win;
     float* inten;
-    float* out;
+    float* out;                // binned output, or null
+    float* diff;               // [p][m][m] intensities (4D output), or null
     const int* perm;
     const int* bin_start;
     const float2* tw_m;
     int n_probes, n_bins;
+    float scale;               // binned output = scale * sum (+ previous value when accumulating)
+    int accumulate;
 };
 // All jobs of one window side m (one launch per 24 jobs for m <= 128).
 hipError_t launch_window_batch(int m, const WindowArgs* jobs, int n_jobs, hipStream_t st);
 
 // out[p][bin] = sum over bin pixels of inten[p][pix] (deterministic order).
 hipError_t launch_bin_reduce(const float* inten, int64_t pix_per_item, float* out, const int* perm,
-                             const int* bin_start, int n_items, int n_bins, hipStream_t st);
+                             const int* bin_start, int n_items, int n_bins, hipStream_t st, float scale = 1.f,
+                             int accumulate = 0);
 
 }  // namespace prism

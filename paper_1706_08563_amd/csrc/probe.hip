@@ -15,7 +15,8 @@ constexpr int WG = 256;
 // C[p][b] = amp e^{-2 pi i (kx x + ky y)/L}; the phase argument is formed in
 // FP64 and reduced to [-1/2, 1/2] turns before the FP32 sincos.
 __global__ __launch_bounds__(WG) void k_coefficients(float2* __restrict__ C, const double2* __restrict__ xy,
-                                                     const int2* __restrict__ beams, int n_probes, int n_beams,
+                                                     const int2* __restrict__ beams,
+                                                     const float2* __restrict__ aberr, int n_probes, int n_beams,
                                                      double inv_L, float amp) {
     int64_t total = (int64_t)n_probes * n_beams;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
@@ -26,18 +27,20 @@ __global__ __launch_bounds__(WG) void k_coefficients(float2* __restrict__ C, con
         float fr = (float)(a - rint(a));
         float s, c;
         sincosf(-6.283185307179586f * fr, &s, &c);
-        C[i] = make_float2(amp * c, amp * s);
+        float2 v = make_float2(amp * c, amp * s);
+        if (aberr) v = cmul(v, aberr[b]);
+        C[i] = v;
     }
 }
 
-hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, int n_probes, int n_beams,
-                               double inv_L, float amp, hipStream_t st) {
+hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, const float2* aberr, int n_probes,
+                               int n_beams, double inv_L, float amp, hipStream_t st) {
     int64_t total = (int64_t)n_probes * n_beams;
     int64_t blocks = (total + WG - 1) / WG;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_coefficients, dim3((unsigned)blocks), dim3(WG), 0, st, C, xy, beams, n_probes, n_beams,
-                       inv_L, amp);
+    hipLaunchKernelGGL(k_coefficients, dim3((unsigned)blocks), dim3(WG), 0, st, C, xy, beams, aberr, n_probes,
+                       n_beams, inv_L, amp);
     return hipGetLastError();
 }
 
@@ -393,12 +396,15 @@ __device__ __forceinline__ float wave_sum(float v) {
 // |Psi|^2 / M^4, then each bin summed over its pixel list by one wavefront.
 struct WindowJob {
     const float2* win;        // [n_probes][m][m]
-    float* out;               // [n_probes][n_bins]
+    float* out;               // [n_probes][n_bins], or null
+    float* diff;              // [n_probes][m][m] intensities (4D output), or null
     const int* perm;          // window pixels grouped by bin
     const int* bin_start;     // [n_bins + 1]
     const float2* tw_m;       // W_m twiddles
     int n_bins;
     int probe0;               // first workgroup of this job
+    float scale;              // out = scale * sum (+ out when accumulating)
+    int accumulate;
 };
 struct WindowBatch {
     int n_jobs;
@@ -415,6 +421,7 @@ __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
     const WindowJob& job = batch.job[jj];
     const float2* __restrict__ win = job.win;
     float* __restrict__ out = job.out;
+    float* __restrict__ diff = job.diff;
     const int* __restrict__ perm = job.perm;
     const int* __restrict__ bin_start = job.bin_start;
     const float2* __restrict__ tw_m = job.tw_m;
@@ -470,6 +477,11 @@ __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
         for (int i = 0; i < E; ++i) col[(lt + LPT * i) * ROW] = make_float2(cnorm(v[i]) * scale, 0.f);
     }
     __syncthreads();
+    if (diff) {
+        float* d = diff + (size_t)p * M * M;
+        for (int idx = tid; idx < M * M; idx += WG) d[idx] = buf[(idx / M) * ROW + F::pad(idx % M)].x;
+    }
+    if (!out) return;
     for (int b = wave; b < n_bins; b += 4) {
         float s = 0.f;
         for (int k = bin_start[b] + lane; k < bin_start[b + 1]; k += 64) {
@@ -477,7 +489,10 @@ __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
             s += buf[(pix / M) * ROW + F::pad(pix % M)].x;
         }
         s = wave_sum(s);
-        if (lane == 0) out[(size_t)p * n_bins + b] = s;
+        if (lane == 0) {
+            float* o = out + (size_t)p * n_bins + b;
+            *o = job.accumulate ? *o + job.scale * s : job.scale * s;
+        }
     }
 }
 
@@ -489,7 +504,8 @@ static hipError_t window_m(const WindowArgs* jobs, int n_jobs, hipStream_t st) {
         int blocks = 0;
         for (int k = 0; k < b.n_jobs; ++k) {
             const WindowArgs& a = jobs[j0 + k];
-            b.job[k] = WindowJob{a.win, a.out, a.perm, a.bin_start, a.tw_m, a.n_bins, blocks};
+            b.job[k] = WindowJob{a.win, a.out, a.diff, a.perm, a.bin_start, a.tw_m, a.n_bins, blocks, a.scale,
+                                 a.accumulate};
             blocks += a.n_probes;
         }
         if (blocks == 0) continue;
@@ -568,7 +584,9 @@ __global__ __launch_bounds__(WG) void k_window_cols(const float2* __restrict__ w
 
 template <int M>
 static hipError_t window_large(float2* win, float* inten, float* out, const int* perm, const int* bin_start,
-                               const float2* tw_m, int n_probes, int n_bins, hipStream_t st) {
+                               const float2* tw_m, int n_probes, int n_bins, float scale, int accumulate,
+                               hipStream_t st) {
+    // inten receives |Psi|^2 / M^4 (it is the 4D output when one is requested)
     constexpr int G = 64 / Fft<M>::LPT;
     const int64_t rows = (int64_t)n_probes * M;
     hipLaunchKernelGGL((k_window_rows<M>), dim3((unsigned)((rows + 4 * G - 1) / (4 * G))), dim3(WG), 0, st, win,
@@ -577,8 +595,8 @@ static hipError_t window_large(float2* win, float* inten, float* out, const int*
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_window_cols<M>), dim3(M / 16, (unsigned)n_probes), dim3(WG), 0, st, win, inten, tw_m);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_bin_reduce(inten, (int64_t)M * M, out, perm, bin_start, n_probes, n_bins, st);
+    if (e != hipSuccess || !out) return e;
+    return launch_bin_reduce(inten, (int64_t)M * M, out, perm, bin_start, n_probes, n_bins, st, scale, accumulate);
 }
 
 hipError_t launch_window_batch(int m, const WindowArgs* jobs, int n_jobs, hipStream_t st) {
@@ -591,10 +609,11 @@ hipError_t launch_window_batch(int m, const WindowArgs* jobs, int n_jobs, hipStr
         case 512:
             for (int k = 0; k < n_jobs; ++k) {
                 const WindowArgs& a = jobs[k];
-                hipError_t e = m == 256 ? window_large<256>(a.win, a.inten, a.out, a.perm, a.bin_start, a.tw_m,
-                                                            a.n_probes, a.n_bins, st)
-                                        : window_large<512>(a.win, a.inten, a.out, a.perm, a.bin_start, a.tw_m,
-                                                            a.n_probes, a.n_bins, st);
+                float* I = a.diff ? a.diff : a.inten;
+                hipError_t e = m == 256 ? window_large<256>(a.win, I, a.out, a.perm, a.bin_start, a.tw_m,
+                                                            a.n_probes, a.n_bins, a.scale, a.accumulate, st)
+                                        : window_large<512>(a.win, I, a.out, a.perm, a.bin_start, a.tw_m,
+                                                            a.n_probes, a.n_bins, a.scale, a.accumulate, st);
                 if (e != hipSuccess) return e;
             }
             return hipSuccess;
@@ -605,7 +624,8 @@ hipError_t launch_window_batch(int m, const WindowArgs* jobs, int n_jobs, hipStr
 // ------------------------------------------------------------- bin reduce --
 __global__ __launch_bounds__(WG) void k_bin_reduce(const float* __restrict__ inten, int64_t pix_per_item,
                                                    float* __restrict__ out, const int* __restrict__ perm,
-                                                   const int* __restrict__ bin_start, int n_bins) {
+                                                   const int* __restrict__ bin_start, int n_bins, float scale,
+                                                   int accumulate) {
     const int item = blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const float* I = inten + (size_t)item * pix_per_item;
@@ -613,14 +633,18 @@ __global__ __launch_bounds__(WG) void k_bin_reduce(const float* __restrict__ int
         float s = 0.f;
         for (int k = bin_start[b] + lane; k < bin_start[b + 1]; k += 64) s += I[perm[k]];
         s = wave_sum(s);
-        if (lane == 0) out[(size_t)item * n_bins + b] = s;
+        if (lane == 0) {
+            float* o = out + (size_t)item * n_bins + b;
+            *o = accumulate ? *o + scale * s : scale * s;
+        }
     }
 }
 
 hipError_t launch_bin_reduce(const float* inten, int64_t pix_per_item, float* out, const int* perm,
-                             const int* bin_start, int n_items, int n_bins, hipStream_t st) {
+                             const int* bin_start, int n_items, int n_bins, hipStream_t st, float scale,
+                             int accumulate) {
     hipLaunchKernelGGL(k_bin_reduce, dim3((unsigned)n_items), dim3(WG), 0, st, inten, pix_per_item, out, perm,
-                       bin_start, n_bins);
+                       bin_start, n_bins, scale, accumulate);
     return hipGetLastError();
 }
 

@@ -220,7 +220,7 @@ hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb
 // ------------------------------------------------------------------ pass B --
 template <int N, int MODE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_WPE))) void k_pass_b(
-    float2* __restrict__ W, PropTables tb, float2* __restrict__ out_half, float* __restrict__ inten,
+    float2* __restrict__ W, PropTables tb, const float2* __restrict__ aux, float* __restrict__ inten,
     const int* __restrict__ ky_max, const double2* __restrict__ probe_xy, double inv_L, float amp, int n_items) {
     using F = Fft<N / 2>;
     constexpr int L = N / 2, E = F::E, LPT = F::LPT, G = 64 / LPT, CPB = 4 * G;
@@ -265,6 +265,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
                 float s, cs;
                 sincosf(-6.283185307179586f * fr, &s, &cs);
                 c = make_float2(amp * cs, amp * s);
+                if (aux) c = cmul(c, aux[(size_t)j * L + jp]);
             }
             e[i] = c;
             o[i] = cmulc(c, btw[i]);
@@ -349,40 +350,40 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
 }
 
 template <int N, int MODE>
-static hipError_t pass_b_nm(float2* W, const PropTables& tb, float2* out_half, float* inten, const int* ky_max,
+static hipError_t pass_b_nm(float2* W, const PropTables& tb, const float2* aux, float* inten, const int* ky_max,
                             const double2* xy, double inv_L, float amp, int n_items, hipStream_t st) {
     constexpr int L = N / 2, LPT = Fft<L>::LPT, CPB = 4 * (64 / LPT) * PassBCols<N, MODE>::value;
     dim3 grid((unsigned)((size_t)n_items * ((L + CPB - 1) / CPB)));
-    hipLaunchKernelGGL((k_pass_b<N, MODE>), grid, dim3(WG), 0, st, W, tb, out_half, inten, ky_max, xy, inv_L, amp,
+    hipLaunchKernelGGL((k_pass_b<N, MODE>), grid, dim3(WG), 0, st, W, tb, aux, inten, ky_max, xy, inv_L, amp,
                        n_items);
     return hipGetLastError();
 }
 
 template <int N>
-static hipError_t pass_b_n(int mode, float2* W, const PropTables& tb, float2* out_half, float* inten,
+static hipError_t pass_b_n(int mode, float2* W, const PropTables& tb, const float2* aux, float* inten,
                            const int* ky_max, const double2* xy, double inv_L, float amp, int n_items,
                            hipStream_t st) {
     switch (mode) {
-        case PASSB_MID: return pass_b_nm<N, PASSB_MID>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
+        case PASSB_MID: return pass_b_nm<N, PASSB_MID>(W, tb, aux, inten, ky_max, xy, inv_L, amp, n_items, st);
         case PASSB_LAST_S:
-            return pass_b_nm<N, PASSB_LAST_S>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
+            return pass_b_nm<N, PASSB_LAST_S>(W, tb, aux, inten, ky_max, xy, inv_L, amp, n_items, st);
         case PASSB_LAST_I:
-            return pass_b_nm<N, PASSB_LAST_I>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
-        case PASSB_INIT: return pass_b_nm<N, PASSB_INIT>(W, tb, out_half, inten, ky_max, xy, inv_L, amp, n_items, st);
+            return pass_b_nm<N, PASSB_LAST_I>(W, tb, aux, inten, ky_max, xy, inv_L, amp, n_items, st);
+        case PASSB_INIT: return pass_b_nm<N, PASSB_INIT>(W, tb, aux, inten, ky_max, xy, inv_L, amp, n_items, st);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pass_b(int n, int mode, float2* W, const PropTables& tb, float2* out_half, float* inten,
+hipError_t launch_pass_b(int n, int mode, float2* W, const PropTables& tb, const float2* aux, float* inten,
                          const int* ky_max, const double2* probe_xy, double inv_L, float amp, int n_items,
                          hipStream_t st) {
     switch (n) {
-        case 64: return pass_b_n<64>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
-        case 128: return pass_b_n<128>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
-        case 256: return pass_b_n<256>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
-        case 512: return pass_b_n<512>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
-        case 1024: return pass_b_n<1024>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
-        case 2048: return pass_b_n<2048>(mode, W, tb, out_half, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 64: return pass_b_n<64>(mode, W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 128: return pass_b_n<128>(mode, W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 256: return pass_b_n<256>(mode, W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 512: return pass_b_n<512>(mode, W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 1024: return pass_b_n<1024>(mode, W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
+        case 2048: return pass_b_n<2048>(mode, W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, st);
     }
     return hipErrorInvalidValue;
 }

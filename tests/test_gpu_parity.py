@@ -284,3 +284,80 @@ def test_prism_synthesis_large_windows(P, n, L, f, a, prec):
     err = O.rel_err(out.cpu().numpy().astype(np.float64), ref)
     say(f"  M={d.m_win} beams={d.n_beams}: rel_all={err:.3e}")
     assert err <= TOL
+
+
+# -------------------------------------------------- probe aberrations (C1, C3) --
+@pytest.mark.parametrize("f,C1,C3", [(1, 25.0, 0.0), (2, -60.0, 3.0e5), (4, 0.0, -1.0e6)])
+def test_prism_aberrations(P, f, C1, C3):
+    say(f"prism aberrations f={f} C1={C1} C3={C3}")
+    n = 128
+    w, pos, sp = W.small_workload(n=n, cell=(20.0, 20.0, 6.0), n_atoms=48, f=f, seed=13)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, f)
+    Sg = P.prism_build_smatrix(d, V)
+    xy = W.scan_positions(w.cell, 3, 4)
+    out = P.prism_probe_outputs(d, Sg, P.prism_probe_plan_upload(d, xy, C1=C1, C3=C3), P.PRISM_FP32)
+    _sync()
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    L = w.cell[0]
+    beams = O.beam_set(n, L, d.lambda_, w.alpha_max, f)
+    Sref = O.build_smatrix(Vref, L, w.dz, d.lambda_, d.sigma, beams)
+    ref = O.prism_outputs(Sref, beams, L, n, d.lambda_, f, xy, C1=C1, C3=C3)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "aberrated prism")
+    plain = O.prism_outputs(Sref, beams, L, n, d.lambda_, f, xy)
+    assert O.rel_err(plain, ref) > 1e-3          # the aberration matters here
+
+
+def test_multislice_aberrations(P):
+    say("multislice aberrations C1=-40 C3=2e5")
+    w, pos, sp = W.small_workload(n=128, cell=(20.0, 20.0, 6.0), n_atoms=48, seed=14)
+    g, V = _gpu_potential(P, w, pos, sp)
+    xy = W.scan_positions(w.cell, 2, 3)
+    out = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=4, C1=-40.0, C3=2.0e5)
+    _sync()
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    ref = O.multislice_outputs(Vref, w.cell[0], w.dz, O.wavelength(w.E0), O.interaction_constant(w.E0),
+                               w.alpha_max, xy, C1=-40.0, C3=2.0e5)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "aberrated multislice")
+
+
+# ---------------------------------------------------------------- 4D output --
+@pytest.mark.parametrize("n,L,f,a,prec", [(128, 16.0, 2, 0.02, 0), (256, 20.0, 1, 0.02, 1), (512, 40.0, 1, 0.008, 1)])
+def test_prism_diffraction_4d(P, n, L, f, a, prec):
+    import torch
+    say(f"prism 4D diffraction n={n} f={f} precision={prec}")
+    g = P.prism_grid_init((L, L, 2.0), 2.0, n)
+    d = P.prism_smatrix_plan(g, 200e3, a, f)
+    rng = np.random.default_rng(41 + n)
+    S = W.random_complex((d.n_beams, d.ns, d.ns), rng)
+    xy = np.concatenate([W.random_positions((L, L), 6, rng), [[0.0, 0.0]]])
+    plan = P.prism_probe_plan_upload(d, xy, C1=15.0)
+    St = torch.tensor(S, device="cuda")
+    I = P.prism_probe_diffraction(d, St, plan, prec)
+    D = P.prism_probe_outputs(d, St, plan, prec)
+    _sync()
+    beams = P.prism_beam_list(d).astype(np.int64)
+    ref = O.prism_diffraction(S.astype(np.complex128), beams, L, n, d.lambda_, f, xy, C1=15.0)
+    got = I.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say(f"  M={d.m_win}: 4D rel err {err:.3e}")
+    assert err <= TOL
+    # binning the 4D output gives the 3D output
+    bm = P.prism_detector_bin_map(d.lambda_, L / f, d.alpha_aa, 1e-3, plan.plan.n_bins, d.m_win)
+    Dg = D.cpu().numpy()
+    for p in range(len(xy)):
+        assert np.allclose(O.stem.detect(got[p], bm, Dg.shape[1]), Dg[p], rtol=1e-5, atol=1e-12)
+
+
+# ------------------------------------------------------------ frozen phonons --
+def test_frozen_phonon_average(P):
+    from paper_1706_08563_amd.phonons import frozen_phonon_outputs
+    say("frozen phonons: 3 configurations, n=128, f=2")
+    w, pos, sp = W.small_workload(n=128, cell=(20.0, 20.0, 6.0), n_atoms=40, seed=15)
+    cfgs = W.thermal_configs(pos, 0.08, 3, seed=7)
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    xy = W.scan_positions(w.cell, 3, 3)
+    out = frozen_phonon_outputs(g, w.E0, w.alpha_max, 2, cfgs, sp, w.species, xy, precision=P.PRISM_SPLIT_BF16X3)
+    _sync()
+    ref = O.frozen_phonon_prism(cfgs, sp, w.species, w.cell, w.dz, w.n, w.E0, w.alpha_max, 2, xy)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "frozen-phonon mean")

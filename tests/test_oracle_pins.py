@@ -394,3 +394,106 @@ def test_probe_window_is_periodic_crop_at_centre_minus_half():
     assert O.window_centre(0.15, L, n) == 0 and O.window_centre(0.16, L, n) == 1
     assert O.window_centre(0.3125 * 1.5, L, n) == 2
     assert O.window_centre(9.9, L, n) == 0 and O.window_centre(-0.2, L, n) == 31
+
+
+# ---------------------------------------------------------------------------
+# Aberrations carried by the probe coefficients.  Defocus C1 with the Eq. (2)
+# propagator is free propagation over C1: a probe defocused by m dz equals the
+# in-focus probe sent through m vacuum slices first.
+# ---------------------------------------------------------------------------
+def test_defocus_equals_vacuum_slices_in_front():
+    w, pos, sp = W.small_workload(n=64, n_atoms=14, seed=9)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    L = w.cell[0]
+    V = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    m = 3
+    Vpad = np.concatenate([np.zeros((m,) + V.shape[1:]), V], axis=0)
+    xy = (3.7, 6.2)
+    a = O.multislice_exit_spectrum(V, L, w.dz, lam, sig, w.alpha_max, xy, C1=m * w.dz)
+    b = O.multislice_exit_spectrum(Vpad, L, w.dz, lam, sig, w.alpha_max, xy)
+    assert np.max(np.abs(a - b)) < 1e-10 * np.max(np.abs(b))
+    # and defocus changes the result (the test is not vacuous)
+    c = O.multislice_exit_spectrum(V, L, w.dz, lam, sig, w.alpha_max, xy)
+    assert np.max(np.abs(np.abs(a) - np.abs(c))) > 1e-3 * np.max(np.abs(c))
+
+
+def test_aberrated_prism_f1_equals_aberrated_multislice():
+    w, pos, sp = W.small_workload(n=64, n_atoms=16, seed=10, f=1)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    L = w.cell[0]
+    V = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    xy = np.array([[0.0, 0.0], [5.5, 2.5]])
+    kw = dict(C1=-40.0, C3=2.0e5)
+    Dm = O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy, **kw)
+    beams = O.beam_set(w.n, L, lam, w.alpha_max, 1)
+    Dp = O.prism_outputs(O.build_smatrix(V, L, w.dz, lam, sig, beams), beams, L, w.n, lam, 1, xy, **kw)
+    assert O.rel_err(Dp, Dm) < 1e-10
+    assert O.rel_err(Dm, O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy)) > 1e-3
+
+
+def test_aberration_phase_spherical_term_as_local_defocus():
+    # On a thin ring |q| ~ q0 the C3 term equals a defocus C3 lam^2 q0^2 up to
+    # a constant and a second-order remainder (pi/2) C3 lam^3 (q^2 - q0^2)^2.
+    lam, L = 0.025, 100.0
+    beams = np.array([[40, 0], [0, 41], [29, 29], [-39, 9]])
+    q2 = (beams[:, 0] / L) ** 2 + (beams[:, 1] / L) ** 2
+    q0sq = 0.16
+    C3 = 1.0e6
+    chi = O.aberration_phase(beams, L, lam, C3=C3)
+    local = O.aberration_phase(beams, L, lam, C1=C3 * lam ** 2 * q0sq) - 0.5 * math.pi * C3 * lam ** 3 * q0sq ** 2
+    rem = 0.5 * math.pi * C3 * lam ** 3 * (q2 - q0sq) ** 2
+    assert np.max(np.abs(chi - local - rem)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# 4D output: the full diffraction pattern per probe.
+# ---------------------------------------------------------------------------
+def test_diffraction_vacuum_peaks_and_parseval():
+    n, L, E0, a, f = 64, 10.0, 80e3, 0.02, 2
+    lam, sig = O.wavelength(E0), O.interaction_constant(E0)
+    beams = O.beam_set(n, L, lam, a, f)
+    S = O.build_smatrix(np.zeros((2, n, n)), L, 2.0, lam, sig, beams)
+    xy = np.array([[1.0, 2.0], [7.5, 0.3]])
+    I = O.prism_diffraction(S, beams, L, n, lam, f, xy)
+    M = n // 2 // f
+    # vacuum: one peak 1/|B| at every beam's window frequency k/f, zero elsewhere
+    expected = np.zeros((M, M))
+    for kx, ky in beams:
+        expected[(ky // f) % M, (kx // f) % M] = 1.0 / len(beams)
+    assert np.max(np.abs(I - expected[None])) < 1e-14
+
+
+def test_diffraction_bins_sum_to_3d_output():
+    w, pos, sp = W.small_workload(n=64, n_atoms=12, seed=11)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    L = w.cell[0]
+    V = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    beams = O.beam_set(w.n, L, lam, w.alpha_max, 2)
+    S = O.build_smatrix(V, L, w.dz, lam, sig, beams)
+    xy = np.array([[2.0, 3.0], [9.0, 1.0]])
+    I = O.prism_diffraction(S, beams, L, w.n, lam, 2, xy)
+    D = O.prism_outputs(S, beams, L, w.n, lam, 2, xy)
+    M = w.n // 4
+    bm = O.bin_map(lam, M, L / 2, O.alpha_aa(lam, w.n, L), 1e-3, D.shape[1])
+    for p in range(len(xy)):
+        assert np.allclose(O.stem.detect(I[p], bm, D.shape[1]), D[p], rtol=0, atol=1e-15)
+    # Parseval: total intensity equals the window's mean squared amplitude
+    C = O.probe_coefficients(beams, L, xy)
+    cx, cy = O.window_centre(xy[0, 0], L, w.n), O.window_centre(xy[0, 1], L, w.n)
+    win = O.probe_window(S, C[0], cx, cy, M)
+    assert abs(I[0].sum() - np.sum(np.abs(win) ** 2) / M ** 2) < 1e-12
+
+
+def test_frozen_phonon_average_of_identical_configs_is_single_run():
+    w, pos, sp = W.small_workload(n=64, n_atoms=10, seed=12)
+    lam = O.wavelength(w.E0)
+    xy = np.array([[1.0, 1.0], [6.0, 4.0]])
+    one = O.frozen_phonon_prism([pos], sp, w.species, w.cell, w.dz, w.n, w.E0, w.alpha_max, 2, xy)
+    three = O.frozen_phonon_prism([pos, pos, pos], sp, w.species, w.cell, w.dz, w.n, w.E0, w.alpha_max, 2, xy)
+    assert O.rel_err(three, one) < 1e-14
+    # and the mean of two different configurations is the mean of their runs
+    cfgs = W.thermal_configs(pos, 0.1, 2, seed=5)
+    two = O.frozen_phonon_prism(cfgs, sp, w.species, w.cell, w.dz, w.n, w.E0, w.alpha_max, 2, xy)
+    singles = [O.frozen_phonon_prism([c], sp, w.species, w.cell, w.dz, w.n, w.E0, w.alpha_max, 2, xy) for c in cfgs]
+    assert O.rel_err(two, 0.5 * (singles[0] + singles[1])) < 1e-14
+    assert O.rel_err(singles[0], singles[1]) > 1e-4

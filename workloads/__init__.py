@@ -202,3 +202,11 @@ def serving_sample(cell, seed: int):
         pos, sp = nanoparticle_in_amorphous(cell, rng=np.random.default_rng(seed))
         return pos, sp, (AU, C)
     return make
+
+
+def thermal_configs(pos, sigma: float, n_configs: int, seed: int):
+    """Frozen-phonon configurations: `pos` displaced by independent Gaussian
+    offsets of standard deviation `sigma` (A) per coordinate."""
+    rng = np.random.default_rng(seed)
+    pos = np.asarray(pos, dtype=np.float64)
+    return [pos + rng.normal(0.0, sigma, size=pos.shape) for _ in range(n_configs)]
