@@ -249,6 +249,73 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
                        const float* V, const double* probe_xy, int64_t n_probes, double dalpha,
                        int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- streaming memory model ("Streaming Data for Very Large Simulations") --- */
+/* For cells whose potential or S-matrix should not be resident in device
+ * memory: the large arrays stay in host memory (page-locked, e.g. from
+ * hipHostMalloc, for the copies to be asynchronous) and only the subset the
+ * current step needs is staged through small device buffers.  Copies are
+ * issued on the caller's copy streams and overlap the kernels running on the
+ * compute stream; each staging buffer is double-buffered and guarded by HIP
+ * events, so the copy of the next slice (or beam chunk) proceeds while the
+ * current one is processed.  The results are those of the single-transfer
+ * entry points: the build and multislice give bit-identical outputs; the
+ * streamed synthesis sums its beam chunks in order into FP32 windows.
+ *
+ * Streams: `stream` runs the kernels; `h2d_stream` and `d2h_stream` carry
+ * the host-to-device and device-to-host copies (they may be the same stream,
+ * or `stream` itself, at the cost of overlap).  The copies start after the
+ * work enqueued on `stream` before the call.  On return all work is enqueued
+ * and `stream` is made to wait for every copy, so the results (including
+ * host-side S) are complete once `stream` has drained.  The host
+ * arrays must stay alive and unmodified until then.  HIP events are created
+ * and destroyed per call; no device memory is allocated. */
+
+/* Device workspace of prism_build_smatrix_streaming: two potential-slice
+ * buffers, one transmission slice, the wave buffer of one beam batch and two
+ * S staging buffers of one batch. */
+int prism_streaming_build_workspace(const prism_smatrix_desc* d, size_t* bytes);
+
+/* Same S-matrix as prism_build_smatrix (bit-identical), with V in host memory
+ * (float32 [n_slices][n][n]) and S written to host memory
+ * (complex64 [n_beams][ns][ns]).  Every beam batch streams all slices of V
+ * (one slice ahead) and its finished S layers are copied out while the next
+ * batch runs.
+ * Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
+int prism_build_smatrix_streaming(const prism_smatrix_desc* d, const float* V_host, void* S_host,
+                                  void* ws, size_t ws_bytes, void* stream, void* h2d_stream,
+                                  void* d2h_stream);
+
+/* Device workspace of prism_probe_outputs_streaming with beam_chunk beams
+ * staged at a time (two S chunk buffers, the coefficients of one chunk, the
+ * windows of all probes). */
+int prism_probe_streaming_workspace(const prism_smatrix_desc* d, const prism_probe_plan* plan,
+                                    int32_t beam_chunk, size_t* bytes);
+
+/* prism_probe_outputs (out, or the 4D output out4d when out is NULL) with S in
+ * host memory (complex64 [n_beams][ns][ns]): beam chunks are copied in one
+ * chunk ahead and their windowed contractions accumulate into the FP32
+ * windows before the window transform.  beam_chunk in [1, n_beams].
+ * Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
+int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_host,
+                                  const prism_probe_plan* plan, const void* plan_dev,
+                                  int32_t precision, int32_t beam_chunk, float* out, float* out4d,
+                                  void* ws, size_t ws_bytes, void* stream, void* h2d_stream);
+
+/* Device workspace of multislice_outputs_streaming. */
+int multislice_streaming_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes,
+                                   size_t* bytes);
+
+/* multislice_outputs (bit-identical) with V in host memory (float32
+ * [n_slices][n][n]): each probe batch streams the slices one ahead through
+ * two device slice buffers, as the paper's streaming multislice keeps only
+ * the current slice of the potential on the device.
+ * Errors: as multislice_outputs. */
+int multislice_outputs_streaming(const prism_grid* grid, double E0, double alpha_max,
+                                 const prism_aberrations* ab, const float* V_host,
+                                 const double* probe_xy, int64_t n_probes, double dalpha,
+                                 int32_t n_bins, int32_t batch, float* out, void* ws,
+                                 size_t ws_bytes, void* stream, void* h2d_stream);
+
 /* ---- detector geometry ------------------------------------------------------ */
 
 /* map[ky][kx] (host int32 [m][m], FFT order) = floor(alpha / dalpha) with

@@ -16,4 +16,7 @@ from .api import (  # noqa: F401
     prism_probe_outputs, multislice_outputs, multislice_workspace, ProbePlan,
     prism_timing_enable, prism_timing_reset, prism_timing_read,
     prism_probe_batch_workspace, prism_probe_outputs_batched, prism_probe_diffraction,
+    prism_streaming_build_workspace, prism_build_smatrix_streaming, prism_probe_streaming_workspace,
+    prism_probe_outputs_streaming, multislice_streaming_workspace, multislice_outputs_streaming,
 )
+from . import _lib  # noqa: F401

@@ -89,6 +89,18 @@ _SIGNATURES = {
     "multislice_workspace": ([POINTER(prism_grid), c_int32, c_int64, POINTER(c_size_t)], c_int32),
     "multislice_outputs": ([POINTER(prism_grid), c_double, c_double, POINTER(prism_aberrations), c_void_p, c_void_p,
                             c_int64, c_double, c_int32, c_int32, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
+    "prism_streaming_build_workspace": ([POINTER(prism_smatrix_desc), POINTER(c_size_t)], c_int32),
+    "prism_build_smatrix_streaming": ([POINTER(prism_smatrix_desc), c_void_p, c_void_p, c_void_p, c_size_t,
+                                       c_void_p, c_void_p, c_void_p], c_int32),
+    "prism_probe_streaming_workspace": ([POINTER(prism_smatrix_desc), POINTER(prism_probe_plan), c_int32,
+                                         POINTER(c_size_t)], c_int32),
+    "prism_probe_outputs_streaming": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p,
+                                       c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
+                                       c_void_p], c_int32),
+    "multislice_streaming_workspace": ([POINTER(prism_grid), c_int32, c_int64, POINTER(c_size_t)], c_int32),
+    "multislice_outputs_streaming": ([POINTER(prism_grid), c_double, c_double, POINTER(prism_aberrations), c_void_p,
+                                      c_void_p, c_int64, c_double, c_int32, c_int32, c_void_p, c_void_p, c_size_t,
+                                      c_void_p, c_void_p], c_int32),
     "prism_detector_bin_map": ([c_double, c_double, c_double, c_double, c_int32, c_int32, c_void_p], c_int32),
     "prism_timing_enable": ([c_int32], c_int32),
     "prism_timing_reset": ([], c_int32),

@@ -224,6 +224,94 @@ def multislice_outputs(grid: prism_grid, E0: float, alpha_max: float, V, xy, dal
     return out
 
 
+# ------------------------------------------- streaming memory model --
+def _pinned(shape, dtype):
+    torch = _torch()
+    return torch.empty(shape, dtype=dtype, pin_memory=True)
+
+
+def _side_stream(st):
+    return st if st is not None else _torch().cuda.Stream()
+
+
+def prism_streaming_build_workspace(d: prism_smatrix_desc) -> int:
+    need = ctypes.c_size_t()
+    check(lib.prism_streaming_build_workspace(ctypes.byref(d), ctypes.byref(need)))
+    return need.value
+
+
+def prism_build_smatrix_streaming(d: prism_smatrix_desc, V_host, S_host=None, ws=None, h2d=None, d2h=None):
+    """S-matrix into host memory (complex64 [n_beams, ns, ns], page-locked) from
+    a host potential V_host (float32 [n_slices, n, n]); complete once the
+    current stream has drained."""
+    torch = _torch()
+    assert V_host.device.type == "cpu" and V_host.dtype == torch.float32 and V_host.is_contiguous()
+    if S_host is None:
+        S_host = _pinned((d.n_beams, d.ns, d.ns), torch.complex64)
+    if ws is None:
+        ws = _workspace(prism_streaming_build_workspace(d))
+    h2d, d2h = _side_stream(h2d), _side_stream(d2h)
+    check(lib.prism_build_smatrix_streaming(ctypes.byref(d), _dev(V_host), _dev(S_host), _dev(ws), ws.numel(),
+                                            _stream(), ctypes.c_void_p(h2d.cuda_stream),
+                                            ctypes.c_void_p(d2h.cuda_stream)))
+    return S_host
+
+
+def prism_probe_streaming_workspace(d: prism_smatrix_desc, plan: ProbePlan, beam_chunk: int) -> int:
+    need = ctypes.c_size_t()
+    check(lib.prism_probe_streaming_workspace(ctypes.byref(d), ctypes.byref(plan.plan), int(beam_chunk),
+                                              ctypes.byref(need)))
+    return need.value
+
+
+def prism_probe_outputs_streaming(d: prism_smatrix_desc, S_host, plan: ProbePlan, precision: int = PRISM_FP32,
+                                  beam_chunk: int = 128, ws=None, out=None, diffraction: bool = False, h2d=None):
+    """Probe outputs (or the 4D output with diffraction=True) from a host
+    S-matrix streamed in beam chunks."""
+    torch = _torch()
+    assert S_host.device.type == "cpu" and S_host.dtype == torch.complex64 and S_host.is_contiguous()
+    p = plan.plan
+    if out is None:
+        shape = (p.n_probes, d.m_win, d.m_win) if diffraction else (p.n_probes, p.n_bins)
+        out = torch.empty(shape, dtype=torch.float32, device=plan.dev.device)
+    if ws is None:
+        ws = _workspace(prism_probe_streaming_workspace(d, plan, beam_chunk), plan.dev.device)
+    h2d = _side_stream(h2d)
+    o3, o4 = (None, _dev(out)) if diffraction else (_dev(out), None)
+    check(lib.prism_probe_outputs_streaming(ctypes.byref(d), _dev(S_host), ctypes.byref(p), _dev(plan.dev),
+                                            int(precision), int(beam_chunk), o3, o4, _dev(ws), ws.numel(),
+                                            _stream(), ctypes.c_void_p(h2d.cuda_stream)))
+    return out
+
+
+def multislice_streaming_workspace(grid: prism_grid, batch: int, n_probes: int) -> int:
+    need = ctypes.c_size_t()
+    check(lib.multislice_streaming_workspace(ctypes.byref(grid), int(batch), int(n_probes), ctypes.byref(need)))
+    return need.value
+
+
+def multislice_outputs_streaming(grid: prism_grid, E0: float, alpha_max: float, V_host, xy, dalpha: float = 1e-3,
+                                 n_bins: int = 0, batch: int = 64, ws=None, out=None, C1: float = 0.0,
+                                 C3: float = 0.0, h2d=None):
+    """multislice_outputs with the potential in host memory, streamed a slice ahead."""
+    torch = _torch()
+    assert V_host.device.type == "cpu" and V_host.dtype == torch.float32 and V_host.is_contiguous()
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    if n_bins <= 0:
+        f = max(1, (grid.n // 2) // 128)
+        n_bins = int(np.ceil(prism_smatrix_plan(grid, E0, alpha_max, f).alpha_aa / dalpha))
+    if ws is None:
+        ws = _workspace(multislice_streaming_workspace(grid, batch, len(xy)))
+    if out is None:
+        out = torch.empty((len(xy), n_bins), dtype=torch.float32, device=ws.device)
+    h2d = _side_stream(h2d)
+    check(lib.multislice_outputs_streaming(ctypes.byref(grid), float(E0), float(alpha_max), _aberrations(C1, C3),
+                                           _dev(V_host), xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha),
+                                           int(n_bins), int(batch), _dev(out), _dev(ws), ws.numel(), _stream(),
+                                           ctypes.c_void_p(h2d.cuda_stream)))
+    return out
+
+
 # ---------------------------------------------------------------- timing --
 def prism_timing_enable(enable: bool = True):
     check(lib.prism_timing_enable(1 if enable else 0))

@@ -721,142 +721,447 @@ int prism_probe_outputs_batched(const prism_probe_job* jobs, int32_t n_jobs, int
 }
 
 // ------------------------------------------------------------ multislice --
-static void multislice_carve(Carve& c, int n, int nsl, int64_t n_probes, int batch, int n_bins, size_t n_binned,
-                             PropDev& pd, int*& kymax, int*& perm, int*& bstart, double2*& xy, float2*& T,
-                             float2*& W, float*& I, float2*& aberr) {
-    pd = carve_prop(c, n);
-    aberr = c.take<float2>((size_t)(n / 2) * (n / 2));
-    kymax = c.take<int>(n / 2);
-    perm = c.take<int>(std::max<size_t>(n_binned, 1));
-    bstart = c.take<int>(n_bins + 1);
-    xy = c.take<double2>((size_t)std::max<int64_t>(n_probes, 1));
-    T = c.take<float2>((size_t)nsl * n * n);
-    W = c.take<float2>((size_t)batch * (n / 2) * wave_col_stride(n));
-    I = c.take<float>((size_t)batch * (n / 2) * (n / 2));
-}
+// Host side of a multislice call: aperture, aberration table, bin tables.
+struct MsHost {
+    double lam, sig, a_aa;
+    int n_bins;
+    long long n_ap;
+    std::vector<int> kymax, perm, bstart;
+    std::vector<float2> aberr;
+    std::vector<double2> xy;
+};
 
-int multislice_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes, size_t* bytes) {
-    int rc = check_grid(grid);
-    if (rc) return rc;
-    if (!bytes || batch < 1 || n_probes < 0) return fail(PRISM_E_INVAL, "multislice workspace: invalid argument");
-    const int n = grid->n;
-    Carve c(nullptr);
-    PropDev pd;
-    int *a, *b, *e;
-    double2* xy;
-    float2 *T, *W, *ab;
-    float* I;
-    // bins can cover at most the (n/2)^2 band pixels
-    multislice_carve(c, n, grid->n_slices, n_probes, batch, 4096, (size_t)(n / 2) * (n / 2), pd, a, b, e, xy, T, W, I,
-                     ab);
-    *bytes = c.off + 256;
-    return PRISM_OK;
-}
-
-int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
-                       const float* V, const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins,
-                       int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream) {
-    int rc = check_grid(grid);
-    if (rc) return rc;
-    if (!V || !out || (n_probes > 0 && !probe_xy) || n_probes < 0 || batch < 1 || !(E0 > 0) || !(alpha_max > 0) ||
-        !(dalpha > 0))
-        return fail(PRISM_E_INVAL, "multislice: invalid argument");
-    const int n = grid->n, Lh = n / 2, nsl = grid->n_slices;
+static int multislice_host(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                           const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins, MsHost& h) {
+    const int n = grid->n, Lh = n / 2;
     const double L = grid->cell[0];
-    const double lam = wavelength_A(E0), sig = sigma_per_VA(E0), a_aa = alpha_aa_of(lam, n, L);
-    if (!(alpha_max < a_aa))
-        return fail(PRISM_E_UNSUPPORTED, "multislice: alpha_max %.6g must be below alpha_AA %.6g", alpha_max, a_aa);
-    if (n_bins <= 0) n_bins = default_bins(a_aa, dalpha);
+    h.lam = wavelength_A(E0);
+    h.sig = sigma_per_VA(E0);
+    h.a_aa = alpha_aa_of(h.lam, n, L);
+    if (!(alpha_max < h.a_aa))
+        return fail(PRISM_E_UNSUPPORTED, "multislice: alpha_max %.6g must be below alpha_AA %.6g", alpha_max, h.a_aa);
+    if (n_bins <= 0) n_bins = default_bins(h.a_aa, dalpha);
     if (n_bins > 4096) return fail(PRISM_E_UNSUPPORTED, "multislice: more than 4096 bins");
-    size_t need = 0;
-    rc = multislice_workspace(grid, batch, n_probes, &need);
-    if (rc) return rc;
-    if (!ws || ws_bytes < need) return fail(PRISM_E_WORKSPACE, "multislice: workspace %zu < %zu bytes", ws_bytes, need);
+    h.n_bins = n_bins;
     // aperture per band column and its size
-    std::vector<int> kymax(Lh, -1);
-    long long n_ap = 0;
+    h.kymax.assign(Lh, -1);
+    h.n_ap = 0;
     for (int j = 0; j < Lh; ++j) {
         int kx = band_k(j, n);
         int m = -1;
-        while (m + 1 < n / 4 && angle_of(lam, kx, m + 1, L) <= alpha_max) ++m;
-        kymax[j] = m;
-        if (m >= 0) n_ap += 2 * m + 1;
+        while (m + 1 < n / 4 && angle_of(h.lam, kx, m + 1, L) <= alpha_max) ++m;
+        h.kymax[j] = m;
+        if (m >= 0) h.n_ap += 2 * m + 1;
     }
-    if (n_ap == 0) return fail(PRISM_E_INVAL, "multislice: empty aperture");
+    if (h.n_ap == 0) return fail(PRISM_E_INVAL, "multislice: empty aperture");
     // aberration factor of every band pixel [j][j'] (kx from j, ky from j')
     const double C1 = ab ? ab->C1 : 0.0, C3 = ab ? ab->C3 : 0.0;
     if (!std::isfinite(C1) || !std::isfinite(C3)) return fail(PRISM_E_INVAL, "multislice: non-finite aberrations");
-    std::vector<float2> aberr;
     if (C1 != 0.0 || C3 != 0.0) {
-        aberr.resize((size_t)Lh * Lh);
+        h.aberr.resize((size_t)Lh * Lh);
         for (int j = 0; j < Lh; ++j)
             for (int jp = 0; jp < Lh; ++jp)
-                aberr[(size_t)j * Lh + jp] = aberration_factor(band_k(j, n), band_k(jp, n), L, lam, C1, C3);
+                h.aberr[(size_t)j * Lh + jp] = aberration_factor(band_k(j, n), band_k(jp, n), L, h.lam, C1, C3);
     }
     // bins over band pixels, index j * (n/2) + j' (kx from j, ky from j')
     std::vector<int> cnt(n_bins + 1, 0), bins((size_t)Lh * Lh);
     for (int j = 0; j < Lh; ++j)
         for (int jp = 0; jp < Lh; ++jp) {
-            int b = bin_of(lam, band_k(j, n), band_k(jp, n), L, a_aa, dalpha, n_bins);
+            int b = bin_of(h.lam, band_k(j, n), band_k(jp, n), L, h.a_aa, dalpha, n_bins);
             bins[(size_t)j * Lh + jp] = b;
             if (b >= 0) cnt[b + 1]++;
         }
-    std::vector<int> bstart(n_bins + 1, 0);
-    for (int b = 0; b < n_bins; ++b) bstart[b + 1] = bstart[b] + cnt[b + 1];
-    std::vector<int> perm(bstart[n_bins]);
+    h.bstart.assign(n_bins + 1, 0);
+    for (int b = 0; b < n_bins; ++b) h.bstart[b + 1] = h.bstart[b] + cnt[b + 1];
+    h.perm.resize(h.bstart[n_bins]);
     {
-        std::vector<int> fill(bstart.begin(), bstart.end() - 1);
+        std::vector<int> fill(h.bstart.begin(), h.bstart.end() - 1);
         for (size_t i = 0; i < bins.size(); ++i)
-            if (bins[i] >= 0) perm[fill[bins[i]]++] = (int)i;
+            if (bins[i] >= 0) h.perm[fill[bins[i]]++] = (int)i;
     }
-    std::vector<double2> xy(std::max<int64_t>(n_probes, 1));
+    h.xy.resize(std::max<int64_t>(n_probes, 1));
     for (int64_t p = 0; p < n_probes; ++p) {
         if (!std::isfinite(probe_xy[2 * p]) || !std::isfinite(probe_xy[2 * p + 1]))
             return fail(PRISM_E_INVAL, "probe %lld: non-finite position", (long long)p);
-        xy[p] = make_double2(probe_xy[2 * p], probe_xy[2 * p + 1]);
+        h.xy[p] = make_double2(probe_xy[2 * p], probe_xy[2 * p + 1]);
     }
-    Carve c(ws);
+    return PRISM_OK;
+}
+
+// Device layout of a multislice call.  Resident: transmission of every slice.
+// Streaming: one transmission slice and two potential-slice buffers.
+struct MsDev {
     PropDev pd;
-    int *d_kymax, *d_perm, *d_bstart;
-    double2* d_xy;
-    float2 *T, *W, *d_aberr;
+    int *kymax, *perm, *bstart;
+    double2* xy;
+    float2 *T, *W, *aberr;
     float* I;
-    multislice_carve(c, n, nsl, n_probes, batch, n_bins, perm.size(), pd, d_kymax, d_perm, d_bstart, d_xy, T, W, I,
-                     d_aberr);
-    PropHost ph = prop_tables(n, L, lam, grid->dz);
+    float* vslot[2];
+};
+
+static void multislice_carve(Carve& c, int n, int nsl, int64_t n_probes, int batch, int n_bins, size_t n_binned,
+                             bool streaming, MsDev& m) {
+    m.pd = carve_prop(c, n);
+    m.aberr = c.take<float2>((size_t)(n / 2) * (n / 2));
+    m.kymax = c.take<int>(n / 2);
+    m.perm = c.take<int>(std::max<size_t>(n_binned, 1));
+    m.bstart = c.take<int>(n_bins + 1);
+    m.xy = c.take<double2>((size_t)std::max<int64_t>(n_probes, 1));
+    m.T = c.take<float2>((size_t)(streaming ? 1 : nsl) * n * n);
+    m.W = c.take<float2>((size_t)batch * (n / 2) * wave_col_stride(n));
+    m.I = c.take<float>((size_t)batch * (n / 2) * (n / 2));
+    m.vslot[0] = streaming ? c.take<float>((size_t)n * n) : nullptr;
+    m.vslot[1] = streaming ? c.take<float>((size_t)n * n) : nullptr;
+}
+
+static int multislice_ws(const prism_grid* grid, int32_t batch, int64_t n_probes, bool streaming, size_t* bytes) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!bytes || batch < 1 || n_probes < 0) return fail(PRISM_E_INVAL, "multislice workspace: invalid argument");
+    Carve c(nullptr);
+    MsDev m;
+    // bins can cover at most the (n/2)^2 band pixels
+    multislice_carve(c, grid->n, grid->n_slices, n_probes, batch, 4096, (size_t)(grid->n / 2) * (grid->n / 2),
+                     streaming, m);
+    *bytes = c.off + 256;
+    return PRISM_OK;
+}
+
+// Two-slot staging ring: slot k is filled on one stream after `freed[k]`
+// and consumed on another after `ready[k]`.
+struct Ring2 {
+    hipEvent_t ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
+    hipError_t init() {
+        for (int k = 0; k < 2; ++k) {
+            hipError_t e = hipEventCreateWithFlags(&ready[k], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&freed[k], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    ~Ring2() {
+        for (int k = 0; k < 2; ++k) {
+            if (ready[k]) (void)hipEventDestroy(ready[k]);
+            if (freed[k]) (void)hipEventDestroy(freed[k]);
+        }
+    }
+};
+
+// Streamed slice: copy slice s of V_host into slot (g & 1) on h2d once that
+// slot's previous transmission has run, then compute its transmission into T
+// on st.  The caller's next kernels on st read T.
+static int feed_slice(Ring2& r, long long g, const float* V_host, int s, int n, float* const vslot[2], float2* T,
+                      float sigma, hipStream_t st, hipStream_t h2d) {
+    const int k = (int)(g & 1);
+    const size_t n2 = (size_t)n * n;
+    if (r.used[k]) HIP_TRY(hipStreamWaitEvent(h2d, r.freed[k], 0));
+    HIP_TRY(hipMemcpyAsync(vslot[k], V_host + (size_t)s * n2, n2 * sizeof(float), hipMemcpyHostToDevice, h2d));
+    HIP_TRY(hipEventRecord(r.ready[k], h2d));
+    HIP_TRY(hipStreamWaitEvent(st, r.ready[k], 0));
+    HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(vslot[k], T, (int64_t)n2, sigma, st); }));
+    HIP_TRY(hipEventRecord(r.freed[k], st));
+    r.used[k] = true;
+    return PRISM_OK;
+}
+
+// Make `side` wait for all work enqueued so far on st, so that side-stream
+// copies see the results of the caller's earlier work on st.
+static int order_after(hipStream_t side, hipStream_t st) {
+    if (side == st) return PRISM_OK;
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipError_t r = hipEventRecord(e, st);
+    if (r == hipSuccess) r = hipStreamWaitEvent(side, e, 0);
+    (void)hipEventDestroy(e);
+    if (r != hipSuccess) return fail(PRISM_E_DEVICE, "ordering copy stream: %s", hipGetErrorString(r));
+    return PRISM_OK;
+}
+
+// Make st wait for the last use of every slot on the other stream.
+static int join_ring(const Ring2& r, bool on_freed, hipStream_t st) {
+    for (int k = 0; k < 2; ++k)
+        if (r.used[k]) HIP_TRY(hipStreamWaitEvent(st, on_freed ? r.freed[k] : r.ready[k], 0));
+    return PRISM_OK;
+}
+
+static int multislice_run(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                          const float* V, const float* V_host, const double* probe_xy, int64_t n_probes,
+                          double dalpha, int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes,
+                          hipStream_t st, hipStream_t h2d) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    const bool streaming = V_host != nullptr;
+    if ((!V && !V_host) || !out || (n_probes > 0 && !probe_xy) || n_probes < 0 || batch < 1 || !(E0 > 0) ||
+        !(alpha_max > 0) || !(dalpha > 0))
+        return fail(PRISM_E_INVAL, "multislice: invalid argument");
+    const int n = grid->n, Lh = n / 2, nsl = grid->n_slices;
+    const double L = grid->cell[0];
+    MsHost h;
+    rc = multislice_host(grid, E0, alpha_max, ab, probe_xy, n_probes, dalpha, n_bins, h);
+    if (rc) return rc;
+    n_bins = h.n_bins;
+    size_t need = 0;
+    rc = multislice_ws(grid, batch, n_probes, streaming, &need);
+    if (rc) return rc;
+    if (!ws || ws_bytes < need) return fail(PRISM_E_WORKSPACE, "multislice: workspace %zu < %zu bytes", ws_bytes, need);
+    Carve c(ws);
+    MsDev m;
+    multislice_carve(c, n, nsl, n_probes, batch, n_bins, h.perm.size(), streaming, m);
+    PropHost ph = prop_tables(n, L, h.lam, grid->dz);
     std::vector<char> blob;
-    stage(blob, ws, pd.tw_half, ph.tw_half);
-    stage(blob, ws, pd.tw_full, ph.tw_full);
-    stage(blob, ws, pd.band, ph.band);
-    stage(blob, ws, pd.prop, ph.prop);
-    stage(blob, ws, d_kymax, kymax);
-    stage(blob, ws, d_perm, perm);
-    stage(blob, ws, d_bstart, bstart);
-    stage(blob, ws, d_xy, xy);
-    if (!aberr.empty()) stage(blob, ws, d_aberr, aberr);
-    hipStream_t st = as_stream(stream);
+    stage(blob, ws, m.pd.tw_half, ph.tw_half);
+    stage(blob, ws, m.pd.tw_full, ph.tw_full);
+    stage(blob, ws, m.pd.band, ph.band);
+    stage(blob, ws, m.pd.prop, ph.prop);
+    stage(blob, ws, m.kymax, h.kymax);
+    stage(blob, ws, m.perm, h.perm);
+    stage(blob, ws, m.bstart, h.bstart);
+    stage(blob, ws, m.xy, h.xy);
+    if (!h.aberr.empty()) stage(blob, ws, m.aberr, h.aberr);
     rc = upload(ws, blob, st);
     if (rc) return rc;
-    const PropTables tb = pd.tables();
-    HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(V, T, (int64_t)nsl * n * n, (float)sig, st); }));
-    const float amp = (float)(1.0 / std::sqrt((double)n_ap));
+    const PropTables tb = m.pd.tables();
+    Ring2 ring;
+    if (streaming) {
+        HIP_TRY(ring.init());
+        rc = order_after(h2d, st);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(V, m.T, (int64_t)nsl * n * n, (float)h.sig, st); }));
+    }
+    const float amp = (float)(1.0 / std::sqrt((double)h.n_ap));
+    long long g = 0;
     for (int64_t p0 = 0; p0 < n_probes; p0 += batch) {
         const int nb = (int)std::min<int64_t>(batch, n_probes - p0);
         HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
-            return launch_pass_b(n, PASSB_INIT, W, tb, aberr.empty() ? nullptr : d_aberr, nullptr, d_kymax, d_xy + p0,
-                                 1.0 / L, amp, nb, st);
+            return launch_pass_b(n, PASSB_INIT, m.W, tb, h.aberr.empty() ? nullptr : m.aberr, nullptr, m.kymax,
+                                 m.xy + p0, 1.0 / L, amp, nb, st);
         }));
         for (int s = 0; s < nsl; ++s) {
-            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, W, T + (size_t)s * n * n, tb, nullptr, false, nb, st); }));
+            const float2* Ts = m.T + (size_t)s * n * n;
+            if (streaming) {
+                rc = feed_slice(ring, g++, V_host, s, n, m.vslot, m.T, (float)h.sig, st, h2d);
+                if (rc) return rc;
+                Ts = m.T;
+            }
+            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, m.W, Ts, tb, nullptr, false, nb, st); }));
             HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
-                return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_I : PASSB_MID, W, tb, nullptr, I, nullptr, nullptr,
-                                     0.0, 0.f, nb, st);
+                return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_I : PASSB_MID, m.W, tb, nullptr, m.I, nullptr,
+                                     nullptr, 0.0, 0.f, nb, st);
             }));
         }
         HIP_TRY(timed(PRISM_K_BIN_REDUCE, st, [&] {
-            return launch_bin_reduce(I, (int64_t)Lh * Lh, out + p0 * n_bins, d_perm, d_bstart, nb, n_bins, st);
+            return launch_bin_reduce(m.I, (int64_t)Lh * Lh, out + p0 * n_bins, m.perm, m.bstart, nb, n_bins, st);
         }));
     }
+    return PRISM_OK;
+}
+
+int multislice_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes, size_t* bytes) {
+    return multislice_ws(grid, batch, n_probes, false, bytes);
+}
+
+int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                       const float* V, const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins,
+                       int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!V) return fail(PRISM_E_INVAL, "multislice: NULL V");
+    return multislice_run(grid, E0, alpha_max, ab, V, nullptr, probe_xy, n_probes, dalpha, n_bins, batch, out, ws,
+                          ws_bytes, as_stream(stream), nullptr);
+}
+
+int multislice_streaming_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes, size_t* bytes) {
+    return multislice_ws(grid, batch, n_probes, true, bytes);
+}
+
+int multislice_outputs_streaming(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                                 const float* V_host, const double* probe_xy, int64_t n_probes, double dalpha,
+                                 int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream,
+                                 void* h2d_stream) {
+    if (!V_host) return fail(PRISM_E_INVAL, "multislice streaming: NULL V_host");
+    return multislice_run(grid, E0, alpha_max, ab, nullptr, V_host, probe_xy, n_probes, dalpha, n_bins, batch, out,
+                          ws, ws_bytes, as_stream(stream), as_stream(h2d_stream));
+}
+
+// ----------------------------------------------------- streaming S-matrix --
+struct StreamBuildDev {
+    PropDev pd;
+    int2* beams;
+    float* vslot[2];
+    float2 *T, *W;
+    float2* Sst[2];
+};
+
+static void stream_build_carve(Carve& c, const prism_smatrix_desc* d, StreamBuildDev& m) {
+    const int n = d->grid.n, NB = batch_of(d);
+    m.pd = carve_prop(c, n);
+    m.beams = c.take<int2>(d->n_beams);
+    m.vslot[0] = c.take<float>((size_t)n * n);
+    m.vslot[1] = c.take<float>((size_t)n * n);
+    m.T = c.take<float2>((size_t)n * n);
+    m.W = c.take<float2>((size_t)NB * (n / 2) * wave_col_stride(n));
+    m.Sst[0] = c.take<float2>((size_t)NB * d->ns * d->ns);
+    m.Sst[1] = c.take<float2>((size_t)NB * d->ns * d->ns);
+}
+
+int prism_streaming_build_workspace(const prism_smatrix_desc* d, size_t* bytes) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    if (!bytes) return fail(PRISM_E_INVAL, "streaming build workspace: NULL argument");
+    Carve c(nullptr);
+    StreamBuildDev m;
+    stream_build_carve(c, d, m);
+    *bytes = c.off + 256;
+    return PRISM_OK;
+}
+
+int prism_build_smatrix_streaming(const prism_smatrix_desc* d, const float* V_host, void* S_host, void* ws,
+                                  size_t ws_bytes, void* stream, void* h2d_stream, void* d2h_stream) {
+    size_t need = 0;
+    int rc = prism_streaming_build_workspace(d, &need);
+    if (rc) return rc;
+    if (!V_host || !S_host) return fail(PRISM_E_INVAL, "streaming build: NULL V_host or S_host");
+    if (!ws || ws_bytes < need) return fail(PRISM_E_WORKSPACE, "streaming build: workspace %zu < %zu bytes", ws_bytes, need);
+    const int n = d->grid.n, B = d->n_beams, nsl = d->grid.n_slices, NB = batch_of(d);
+    const double L = d->grid.cell[0];
+    const size_t layer = (size_t)d->ns * d->ns;
+    hipStream_t st = as_stream(stream), h2d = as_stream(h2d_stream), d2h = as_stream(d2h_stream);
+    Carve c(ws);
+    StreamBuildDev m;
+    stream_build_carve(c, d, m);
+    PropHost ph = prop_tables(n, L, d->lambda, d->grid.dz);
+    std::vector<char> blob;
+    stage(blob, ws, m.pd.tw_half, ph.tw_half);
+    stage(blob, ws, m.pd.tw_full, ph.tw_full);
+    stage(blob, ws, m.pd.band, ph.band);
+    stage(blob, ws, m.pd.prop, ph.prop);
+    stage(blob, ws, m.beams, beam_list(n, L, d->lambda, d->alpha_max, d->f));
+    rc = upload(ws, blob, st);
+    if (rc) return rc;
+    const PropTables tb = m.pd.tables();
+    Ring2 vr, sr;
+    HIP_TRY(vr.init());
+    HIP_TRY(sr.init());
+    rc = order_after(h2d, st);
+    if (rc) return rc;
+    rc = order_after(d2h, st);
+    if (rc) return rc;
+    float2* Sout = static_cast<float2*>(S_host);
+    long long g = 0;
+    int bi = 0;
+    for (int b0 = 0; b0 < B; b0 += NB, ++bi) {
+        const int nb = std::min(NB, B - b0);
+        const int2* bb = m.beams + b0;
+        for (int s = 0; s < nsl; ++s) {
+            rc = feed_slice(vr, g++, V_host, s, n, m.vslot, m.T, (float)d->sigma, st, h2d);
+            if (rc) return rc;
+            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, m.W, m.T, tb, bb, s == 0, nb, st); }));
+            HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
+                return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, m.W, tb, nullptr, nullptr, nullptr,
+                                     nullptr, 0.0, 0.f, nb, st);
+            }));
+        }
+        // S staging slot k is rewritten once its previous copy-out has run
+        const int k = bi & 1;
+        if (sr.used[k]) HIP_TRY(hipStreamWaitEvent(st, sr.freed[k], 0));
+        HIP_TRY(timed(PRISM_K_FINAL, st, [&] { return launch_smatrix_final(n, m.W, m.Sst[k], m.pd.tw_half, nb, st); }));
+        HIP_TRY(hipEventRecord(sr.ready[k], st));
+        HIP_TRY(hipStreamWaitEvent(d2h, sr.ready[k], 0));
+        HIP_TRY(hipMemcpyAsync(Sout + (size_t)b0 * layer, m.Sst[k], (size_t)nb * layer * sizeof(float2),
+                               hipMemcpyDeviceToHost, d2h));
+        HIP_TRY(hipEventRecord(sr.freed[k], d2h));
+        sr.used[k] = true;
+    }
+    return join_ring(sr, true, st);
+}
+
+// --------------------------------------------------- streaming synthesis --
+struct StreamSynthDev {
+    float2* Sst[2];
+    float2 *C, *win;
+    float* inten;
+};
+
+static void stream_synth_carve(Carve& c, const prism_smatrix_desc* d, const prism_probe_plan* plan, int chunk,
+                               StreamSynthDev& m) {
+    const size_t P = (size_t)std::max<int64_t>(plan->n_probes, 1), M = d->m_win;
+    m.Sst[0] = c.take<float2>((size_t)chunk * d->ns * d->ns);
+    m.Sst[1] = c.take<float2>((size_t)chunk * d->ns * d->ns);
+    m.C = c.take<float2>(P * chunk);
+    m.win = c.take<float2>(P * M * M);
+    m.inten = M > 128 ? c.take<float>(P * M * M) : nullptr;
+}
+
+int prism_probe_streaming_workspace(const prism_smatrix_desc* d, const prism_probe_plan* plan, int32_t beam_chunk,
+                                    size_t* bytes) {
+    int rc = check_desc(d);
+    if (rc) return rc;
+    if (!plan || !bytes || beam_chunk < 1 || beam_chunk > d->n_beams)
+        return fail(PRISM_E_INVAL, "streaming synthesis workspace: invalid argument (beam_chunk in [1, %d])",
+                    d->n_beams);
+    Carve c(nullptr);
+    StreamSynthDev m;
+    stream_synth_carve(c, d, plan, beam_chunk, m);
+    *bytes = c.off + 256;
+    return PRISM_OK;
+}
+
+int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_host, const prism_probe_plan* plan,
+                                  const void* plan_dev, int32_t precision, int32_t beam_chunk, float* out,
+                                  float* out4d, void* ws, size_t ws_bytes, void* stream, void* h2d_stream) {
+    size_t need = 0;
+    int rc = prism_probe_streaming_workspace(d, plan, beam_chunk, &need);
+    if (rc) return rc;
+    if (precision != PRISM_FP32 && precision != PRISM_SPLIT_BF16X3 && precision != PRISM_BF16)
+        return fail(PRISM_E_INVAL, "streaming synthesis: unknown precision %d", precision);
+    if (!S_host || !plan_dev || (!out && !out4d && plan->n_probes > 0))
+        return fail(PRISM_E_INVAL, "streaming synthesis: NULL argument");
+    if (!ws || ws_bytes < need)
+        return fail(PRISM_E_WORKSPACE, "streaming synthesis: workspace %zu < %zu bytes", ws_bytes, need);
+    if (plan->n_probes == 0) return PRISM_OK;
+    hipStream_t st = as_stream(stream), h2d = as_stream(h2d_stream);
+    Carve c(ws);
+    StreamSynthDev m;
+    stream_synth_carve(c, d, plan, beam_chunk, m);
+    const char* pb = static_cast<const char*>(plan_dev);
+    const int P = (int)plan->n_probes, B = d->n_beams, M = d->m_win;
+    const size_t layer = (size_t)d->ns * d->ns;
+    auto xy = reinterpret_cast<const double2*>(pb + plan->off[0]);
+    auto corner = reinterpret_cast<const int2*>(pb + plan->off[1]);
+    auto tstart = reinterpret_cast<const int*>(pb + plan->off[2]);
+    auto tprobes = reinterpret_cast<const int*>(pb + plan->off[3]);
+    auto perm = reinterpret_cast<const int*>(pb + plan->off[4]);
+    auto bstart = reinterpret_cast<const int*>(pb + plan->off[5]);
+    auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
+    auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
+    auto aberr = (plan->C1 != 0.0 || plan->C3 != 0.0) ? reinterpret_cast<const float2*>(pb + plan->off[8]) : nullptr;
+    const float amp = (float)(1.0 / std::sqrt((double)B));
+    const float2* Sh = static_cast<const float2*>(S_host);
+    Ring2 r;
+    HIP_TRY(r.init());
+    rc = order_after(h2d, st);
+    if (rc) return rc;
+    int ci = 0;
+    for (int c0 = 0; c0 < B; c0 += beam_chunk, ++ci) {
+        const int nb = std::min(beam_chunk, B - c0);
+        const int k = ci & 1;
+        if (r.used[k]) HIP_TRY(hipStreamWaitEvent(h2d, r.freed[k], 0));
+        HIP_TRY(hipMemcpyAsync(m.Sst[k], Sh + (size_t)c0 * layer, (size_t)nb * layer * sizeof(float2),
+                               hipMemcpyHostToDevice, h2d));
+        HIP_TRY(hipEventRecord(r.ready[k], h2d));
+        HIP_TRY(hipStreamWaitEvent(st, r.ready[k], 0));
+        HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
+            return launch_coefficients(m.C, xy, beams + c0, aberr ? aberr + c0 : nullptr, P, nb,
+                                       1.0 / d->grid.cell[0], amp, st);
+        }));
+        ContractArgs ca{m.C, m.Sst[k], m.win, tstart, tprobes, corner, plan->n_tiles, plan->max_per_tile, nb, d->ns, M,
+                        ci > 0 ? 1 : 0};
+        HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] { return launch_contract_batch(precision, &ca, 1, st); }));
+        HIP_TRY(hipEventRecord(r.freed[k], st));
+        r.used[k] = true;
+    }
+    WindowArgs wa{m.win, m.inten, out, out4d, perm, bstart, tw_m, P, plan->n_bins, 1.0f, 0};
+    HIP_TRY(timed(PRISM_K_WINDOW, st, [&] { return launch_window_batch(M, &wa, 1, st); }));
     return PRISM_OK;
 }
 

@@ -66,6 +66,7 @@ struct ContractArgs {
     const int* tile_probes;
     const int2* corner;
     int n_tiles, max_per_tile, n_beams, ns, m;
+    int accumulate = 0;       // add to the windows (partial sums over beam chunks)
 };
 // All jobs in as few launches as possible (one per 24 jobs).
 hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_jobs, hipStream_t st);

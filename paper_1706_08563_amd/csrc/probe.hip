@@ -62,6 +62,7 @@ struct ContractJob {
     const int* tile_probes;
     const int2* corner;       // window corner per probe
     int n_beams, ns, m;
+    int accumulate;           // 1: add to the windows' contents (beam chunks of one sum)
     int chunks;               // workgroups per tile (probe chunks)
     int n_tiles;
     int block0;               // first logical workgroup of this job
@@ -77,17 +78,21 @@ struct ContractBatch {
 // Logical workgroup of this hardware workgroup.  Hardware workgroups are
 // dealt round-robin to the 8 XCDs; logical workgroups l and l+1 are placed on
 // the same XCD, so all probe chunks of a pixel tile share that XCD's L2.
-__device__ __forceinline__ const ContractJob* locate(const ContractBatch& b, int& tile, int& chunk) {
+// The selected job is copied out by value: taking the address of the
+// by-value kernel argument would force a private-memory copy of the table.
+__device__ __forceinline__ bool locate(const ContractBatch& b, ContractJob& job, int& tile, int& chunk) {
     const int hw = blockIdx.x;
     const int l = (hw & 7) * b.per_xcd + (hw >> 3);
-    if (l >= b.n_blocks) return nullptr;
+    if (l >= b.n_blocks) return false;
     int j = 0;
-    while (j + 1 < b.n_jobs && b.job[j + 1].block0 <= l) ++j;
-    const ContractJob* job = &b.job[j];
-    const int local = l - job->block0;
-    tile = local / job->chunks;
-    chunk = local % job->chunks;
-    return job;
+#pragma unroll
+    for (int k = 1; k < MAX_JOBS; ++k)
+        if (k < b.n_jobs && b.job[k].block0 <= l) j = k;
+    job = b.job[j];
+    const int local = l - job.block0;
+    tile = local / job.chunks;
+    chunk = local % job.chunks;
+    return true;
 }
 
 namespace fp32c {
@@ -100,15 +105,15 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
     __shared__ float2 cs[KB][PC];
     __shared__ int pidx[PC];
     int tile, chunk;
-    const ContractJob* job = locate(batch, tile, chunk);
-    if (!job) return;
-    const float2* __restrict__ C = job->C;
-    const float2* __restrict__ S = job->S;
-    float2* __restrict__ win = job->win;
-    const int* __restrict__ tile_probes = job->tile_probes;
-    const int2* __restrict__ corner = job->corner;
-    const int n_beams = job->n_beams, ns = job->ns, m = job->m;
-    const int t0 = job->tile_start[tile], t1 = job->tile_start[tile + 1];
+    ContractJob job;
+    if (!locate(batch, job, tile, chunk)) return;
+    const float2* __restrict__ C = job.C;
+    const float2* __restrict__ S = job.S;
+    float2* __restrict__ win = job.win;
+    const int* __restrict__ tile_probes = job.tile_probes;
+    const int2* __restrict__ corner = job.corner;
+    const int n_beams = job.n_beams, ns = job.ns, m = job.m;
+    const int t0 = job.tile_start[tile], t1 = job.tile_start[tile + 1];
     const int pc0 = t0 + chunk * PC;
     if (pc0 >= t1) return;
     const int np = min(PC, t1 - pc0);
@@ -155,7 +160,12 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
             int2 c0 = corner[q];
             int v = (py - c0.y) & (ns - 1);
             int u = (px - c0.x) & (ns - 1);
-            if (v < m && u < m) win[(size_t)q * m * m + (size_t)v * m + u] = acc[p];
+            if (v < m && u < m) {
+                float2* w = win + (size_t)q * m * m + (size_t)v * m + u;
+                float2 r = acc[p];
+                if (job.accumulate) r = cadd(*w, r);
+                *w = r;
+            }
         }
     }
 }
@@ -179,15 +189,18 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-    unsigned int u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
+// Two floats to packed bf16 (round to nearest even, v_cvt_pk_bf16_f32).
+__device__ __forceinline__ unsigned int pack_bf16(float a, float b) {
+    bf16x2 h = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(unsigned int, h);
 }
-__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
-__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
-    hi = bf16_rne(x);
-    lo = bf16_rne(x - bf16_to_f32(hi));
+// x = hi + lo + O(2^-16 |x|): hi = bf16(x), lo = bf16(x - hi), for a pair.
+__device__ __forceinline__ void split_pair(float a, float b, unsigned int& hi, unsigned int& lo) {
+    hi = pack_bf16(a, b);
+    const float ra = __uint_as_float(hi << 16), rb = __uint_as_float(hi & 0xffff0000u);
+    lo = pack_bf16(a - ra, b - rb);
 }
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -195,21 +208,21 @@ template <bool SPLIT>
 __global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
     using namespace mfmac;
     constexpr int NP = SPLIT ? 2 : 1;           // hi (, lo)
-    // [part][re/im][row][beam]: 16 beams of a row contiguous (32 B)
-    __shared__ __attribute__((aligned(16))) unsigned short Ss[NP][2][256][KB];
-    __shared__ __attribute__((aligned(16))) unsigned short Cs[NP][2][PC][KB];
+    // [part][re/im][row][beam]: the 16 beams of a row are contiguous (32 B)
+    __shared__ __attribute__((aligned(16))) u32x4 Ss[NP][2][256][2];
+    __shared__ __attribute__((aligned(16))) uint2 Cs[NP][2][PC][4];
     __shared__ int pidx[PC];
 
     int tile, chunk;
-    const ContractJob* job = locate(batch, tile, chunk);
-    if (!job) return;
-    const float2* __restrict__ C = job->C;
-    const float2* __restrict__ S = job->S;
-    float2* __restrict__ win = job->win;
-    const int* __restrict__ tile_probes = job->tile_probes;
-    const int2* __restrict__ corner = job->corner;
-    const int n_beams = job->n_beams, ns = job->ns, m = job->m;
-    const int t0 = job->tile_start[tile], t1 = job->tile_start[tile + 1];
+    ContractJob job;
+    if (!locate(batch, job, tile, chunk)) return;
+    const float2* __restrict__ C = job.C;
+    const float2* __restrict__ S = job.S;
+    float2* __restrict__ win = job.win;
+    const int* __restrict__ tile_probes = job.tile_probes;
+    const int2* __restrict__ corner = job.corner;
+    const int n_beams = job.n_beams, ns = job.ns, m = job.m;
+    const int t0 = job.tile_start[tile], t1 = job.tile_start[tile + 1];
     const int pc0 = t0 + chunk * PC;
     if (pc0 >= t1) return;
     const int np = min(PC, t1 - pc0);
@@ -227,59 +240,72 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
             acci[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     const size_t plane = (size_t)ns * ns;
-    // S staging: thread = one tile pixel
+    // S staging: thread = one tile pixel, 16 beams per K step
     const int spix = tid;
     const float2* Sp = S + (size_t)(ty0 + spix / TILE) * ns + tx0 + (spix % TILE);
     // C staging: thread = (probe, 4 beams)
     const int cp = tid >> 2, cb = (tid & 3) * 4;
     __syncthreads();
     const int cq = pidx[cp];
+    const float2* Cp = C + (size_t)(cq < 0 ? 0 : cq) * n_beams + cb;
+
+    float2 sv[KB], cv[4];
+    auto load = [&](int b0) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+            sv[k] = (b0 + k < n_beams) ? Sp[(size_t)(b0 + k) * plane] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            cv[k] = (cq >= 0 && b0 + cb + k < n_beams) ? Cp[b0 + k] : make_float2(0.f, 0.f);
+    };
+    load(0);
 
     const int col = lane & 15, g = lane >> 4;   // MFMA operand lane roles
     for (int b0 = 0; b0 < n_beams; b0 += KB) {
-        // ---- stage S: 16 beams of this pixel
+        // ---- convert and stage this K step (16 B stores)
         {
-            unsigned short hr[KB], hi_[KB], lr[KB], li[KB];
+            unsigned int rh[KB / 2], ih[KB / 2], rl[KB / 2], il[KB / 2];
 #pragma unroll
-            for (int k = 0; k < KB; ++k) {
-                float2 v = (b0 + k < n_beams) ? Sp[(size_t)(b0 + k) * plane] : make_float2(0.f, 0.f);
+            for (int k = 0; k < KB / 2; ++k) {
                 if constexpr (SPLIT) {
-                    split_bf16(v.x, hr[k], lr[k]);
-                    split_bf16(v.y, hi_[k], li[k]);
+                    split_pair(sv[2 * k].x, sv[2 * k + 1].x, rh[k], rl[k]);
+                    split_pair(sv[2 * k].y, sv[2 * k + 1].y, ih[k], il[k]);
                 } else {
-                    hr[k] = bf16_rne(v.x);
-                    hi_[k] = bf16_rne(v.y);
+                    rh[k] = pack_bf16(sv[2 * k].x, sv[2 * k + 1].x);
+                    ih[k] = pack_bf16(sv[2 * k].y, sv[2 * k + 1].y);
                 }
             }
-#pragma unroll
-            for (int k = 0; k < KB; ++k) {
-                Ss[0][0][spix][k] = hr[k];
-                Ss[0][1][spix][k] = hi_[k];
-                if constexpr (SPLIT) {
-                    Ss[NP - 1][0][spix][k] = lr[k];
-                    Ss[NP - 1][1][spix][k] = li[k];
-                }
-            }
-        }
-        // ---- stage C: 4 beams of one probe
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            int b = b0 + cb + k;
-            float2 v = (cq >= 0 && b < n_beams) ? C[(size_t)cq * n_beams + b] : make_float2(0.f, 0.f);
+            Ss[0][0][spix][0] = u32x4{rh[0], rh[1], rh[2], rh[3]};
+            Ss[0][0][spix][1] = u32x4{rh[4], rh[5], rh[6], rh[7]};
+            Ss[0][1][spix][0] = u32x4{ih[0], ih[1], ih[2], ih[3]};
+            Ss[0][1][spix][1] = u32x4{ih[4], ih[5], ih[6], ih[7]};
             if constexpr (SPLIT) {
-                unsigned short a0, a1, a2, a3;
-                split_bf16(v.x, a0, a1);
-                split_bf16(v.y, a2, a3);
-                Cs[0][0][cp][cb + k] = a0;
-                Cs[NP - 1][0][cp][cb + k] = a1;
-                Cs[0][1][cp][cb + k] = a2;
-                Cs[NP - 1][1][cp][cb + k] = a3;
-            } else {
-                Cs[0][0][cp][cb + k] = bf16_rne(v.x);
-                Cs[0][1][cp][cb + k] = bf16_rne(v.y);
+                Ss[NP - 1][0][spix][0] = u32x4{rl[0], rl[1], rl[2], rl[3]};
+                Ss[NP - 1][0][spix][1] = u32x4{rl[4], rl[5], rl[6], rl[7]};
+                Ss[NP - 1][1][spix][0] = u32x4{il[0], il[1], il[2], il[3]};
+                Ss[NP - 1][1][spix][1] = u32x4{il[4], il[5], il[6], il[7]};
+            }
+            unsigned int crh[2], cih[2], crl[2], cil[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if constexpr (SPLIT) {
+                    split_pair(cv[2 * k].x, cv[2 * k + 1].x, crh[k], crl[k]);
+                    split_pair(cv[2 * k].y, cv[2 * k + 1].y, cih[k], cil[k]);
+                } else {
+                    crh[k] = pack_bf16(cv[2 * k].x, cv[2 * k + 1].x);
+                    cih[k] = pack_bf16(cv[2 * k].y, cv[2 * k + 1].y);
+                }
+            }
+            Cs[0][0][cp][cb / 4] = make_uint2(crh[0], crh[1]);
+            Cs[0][1][cp][cb / 4] = make_uint2(cih[0], cih[1]);
+            if constexpr (SPLIT) {
+                Cs[NP - 1][0][cp][cb / 4] = make_uint2(crl[0], crl[1]);
+                Cs[NP - 1][1][cp][cb / 4] = make_uint2(cil[0], cil[1]);
             }
         }
         __syncthreads();
+        // ---- next K step's global loads fly while this step's MFMAs run
+        if (b0 + KB < n_beams) load(b0 + KB);
         // ---- B operands: pixel block pb = tile row 4*wave + pb, lane column = pixel
         //      k-group g: 0,1 -> Sr beams 8g.., 2,3 -> Si beams 8(g-2)..
         u32x4 Bop[NP][4];
@@ -288,7 +314,7 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
 #pragma unroll
             for (int pb = 0; pb < 4; ++pb) {
                 const int pix = (4 * wave + pb) * TILE + col;
-                Bop[part][pb] = *reinterpret_cast<const u32x4*>(&Ss[part][g >> 1][pix][8 * (g & 1)]);
+                Bop[part][pb] = Ss[part][g >> 1][pix][g & 1];
             }
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb) {
@@ -297,8 +323,10 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
             u32x4 Ar[NP], Ai[NP];
 #pragma unroll
             for (int part = 0; part < NP; ++part) {
-                u32x4 cr = *reinterpret_cast<const u32x4*>(&Cs[part][0][prow][8 * (g & 1)]);
-                u32x4 ci = *reinterpret_cast<const u32x4*>(&Cs[part][1][prow][8 * (g & 1)]);
+                const uint2* cr2 = &Cs[part][0][prow][2 * (g & 1)];
+                const uint2* ci2 = &Cs[part][1][prow][2 * (g & 1)];
+                u32x4 cr = u32x4{cr2[0].x, cr2[0].y, cr2[1].x, cr2[1].y};
+                u32x4 ci = u32x4{ci2[0].x, ci2[0].y, ci2[1].x, ci2[1].y};
                 if (g < 2) {
                     Ar[part] = cr;
                     Ai[part] = ci;
@@ -340,7 +368,12 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
                 const int py = ty0 + 4 * wave + pb, px = tx0 + col;
                 const int v = (py - c0.y) & (ns - 1);
                 const int u = (px - c0.x) & (ns - 1);
-                if (v < m && u < m) win[(size_t)q * m * m + (size_t)v * m + u] = make_float2(accr[qb][pb][r], acci[qb][pb][r]);
+                if (v < m && u < m) {
+                    float2* w = win + (size_t)q * m * m + (size_t)v * m + u;
+                    float2 res = make_float2(accr[qb][pb][r], acci[qb][pb][r]);
+                    if (job.accumulate) res = cadd(*w, res);
+                    *w = res;
+                }
             }
         }
 }
@@ -363,6 +396,7 @@ hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_
             job.n_beams = a.n_beams;
             job.ns = a.ns;
             job.m = a.m;
+            job.accumulate = a.accumulate;
             job.chunks = (a.max_per_tile + pc - 1) / pc;
             if (job.chunks < 1) job.chunks = 1;
             job.n_tiles = a.n_tiles;
@@ -417,8 +451,10 @@ __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
     constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, ROW = F::LDS + 1;
     __shared__ float2 buf[M * ROW];
     int jj = 0;
-    while (jj + 1 < batch.n_jobs && batch.job[jj + 1].probe0 <= (int)blockIdx.x) ++jj;
-    const WindowJob& job = batch.job[jj];
+#pragma unroll
+    for (int k = 1; k < MAX_JOBS; ++k)
+        if (k < batch.n_jobs && batch.job[k].probe0 <= (int)blockIdx.x) jj = k;
+    const WindowJob job = batch.job[jj];
     const float2* __restrict__ win = job.win;
     float* __restrict__ out = job.out;
     float* __restrict__ diff = job.diff;
