@@ -335,7 +335,8 @@ int prism_detector_bin_map(double lambda, double Lw, double alpha_aa, double dal
 #define PRISM_K_WINDOW         6   /* window FFT, |Psi|^2, detector sums */
 #define PRISM_K_POTENTIAL      7   /* projected potential */
 #define PRISM_K_BIN_REDUCE     8   /* multislice detector sums */
-#define PRISM_TIMING_CLASSES   9
+#define PRISM_K_SPLIT          9   /* S-matrix to split-BF16 tile records (MFMA precisions) */
+#define PRISM_TIMING_CLASSES  10
 
 /* While enabled (per calling thread), every kernel launch of the library is
  * bracketed by HIP events recorded on its stream. */

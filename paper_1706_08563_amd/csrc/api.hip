@@ -319,16 +319,25 @@ int batch_of(const prism_smatrix_desc* d) {
     return (d->beam_batch > 0 && d->beam_batch < d->n_beams) ? d->beam_batch : d->n_beams;
 }
 
-// Workspace of one probe-synthesis job: coefficients, windows and (for
-// windows above 128 pixels) intensities.
-size_t synth_job_bytes(const prism_smatrix_desc* d, const prism_probe_plan* plan, Carve& c) {
+// Workspace of one probe-synthesis job: coefficients (complex64, or the
+// split layout of the MFMA contraction, whichever is larger), windows and
+// (for windows above 128 pixels) intensities.
+struct SynthJobDev {
+    void* C;
+    float2* win;
+    float* inten;
+};
+SynthJobDev synth_job_carve(const prism_smatrix_desc* d, const prism_probe_plan* plan, Carve& c) {
     const size_t P = (size_t)std::max<int64_t>(plan->n_probes, 1);
-    const size_t before = c.off;
-    c.take<float2>(P * d->n_beams);
-    c.take<float2>(P * d->m_win * d->m_win);
-    if (d->m_win > 128) c.take<float>(P * d->m_win * d->m_win);
-    return c.off - before;
+    SynthJobDev j;
+    j.C = c.take<char>(split_c_bytes((int64_t)P, d->n_beams));
+    j.win = c.take<float2>(P * d->m_win * d->m_win);
+    j.inten = d->m_win > 128 ? c.take<float>(P * d->m_win * d->m_win) : nullptr;
+    return j;
 }
+// The MFMA contraction reads S in its split layout, converted once per
+// distinct S-matrix of a call.
+void* split_s_carve(const prism_smatrix_desc* d, Carve& c) { return c.take<char>(split_s_bytes(d->ns, d->n_beams)); }
 
 // Consistency of a descriptor filled by prism_smatrix_plan (without recounting
 // the beams, which costs O(n^2) host work per call).
@@ -580,7 +589,8 @@ int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, i
     p.off[8] = h.aberr.empty() ? 0 : (size_t)c.take<float2>(h.aberr.size());
     p.plan_bytes = c.off + 256;
     Carve w(nullptr);
-    synth_job_bytes(d, &p, w);
+    synth_job_carve(d, &p, w);
+    split_s_carve(d, w);
     p.ws_bytes = w.off + 256;
     *plan = p;
     return PRISM_OK;
@@ -613,6 +623,15 @@ int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
     return upload(plan_dev, blob, as_stream(stream));
 }
 
+// Index of the first job that reads the same S-matrix (same pointer and shape).
+static int first_with_same_s(const prism_probe_job* jobs, int k) {
+    for (int j = 0; j < k; ++j)
+        if (jobs[j].S == jobs[k].S && jobs[j].desc->n_beams == jobs[k].desc->n_beams &&
+            jobs[j].desc->ns == jobs[k].desc->ns)
+            return j;
+    return k;
+}
+
 static int synth_validate(const prism_probe_job* jobs, int n_jobs, int precision, size_t* need) {
     if (!jobs || n_jobs < 0) return fail(PRISM_E_INVAL, "probe outputs: invalid job list");
     if (precision != PRISM_FP32 && precision != PRISM_SPLIT_BF16X3 && precision != PRISM_BF16)
@@ -626,29 +645,46 @@ static int synth_validate(const prism_probe_job* jobs, int n_jobs, int precision
             return fail(PRISM_E_INVAL, "probe outputs: job %d has a NULL pointer", k);
         if (!std::isfinite(jb.out_scale) || (jb.accumulate != 0 && jb.accumulate != 1))
             return fail(PRISM_E_INVAL, "probe outputs: job %d: bad out_scale or accumulate", k);
-        synth_job_bytes(jb.desc, jb.plan, c);
+        synth_job_carve(jb.desc, jb.plan, c);
     }
+    for (int k = 0; k < n_jobs; ++k)
+        if (first_with_same_s(jobs, k) == k) split_s_carve(jobs[k].desc, c);
     *need = c.off + 256;
     return PRISM_OK;
 }
 
 // Probe synthesis for several (S-matrix, probe plan) jobs on one stream:
-// coefficients per job, one contraction launch for all jobs, one window
-// launch per window side.
+// coefficients per job, split S per distinct S-matrix (MFMA precisions), one
+// contraction launch for all jobs, one window launch per window side.
 static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, void* ws, hipStream_t st) {
     std::vector<ContractArgs> ca;
     std::vector<std::vector<WindowArgs>> wa(10);   // by log2(m)
+    const bool split = precision != PRISM_FP32;
     Carve c(ws);
+    std::vector<SynthJobDev> jd(n_jobs);
+    for (int k = 0; k < n_jobs; ++k) jd[k] = synth_job_carve(jobs[k].desc, jobs[k].plan, c);
+    std::vector<const void*> s_op(n_jobs, nullptr);
+    for (int k = 0; k < n_jobs; ++k) {
+        const int j = first_with_same_s(jobs, k);
+        if (j < k) {
+            s_op[k] = s_op[j];
+            continue;
+        }
+        void* ss = split_s_carve(jobs[k].desc, c);
+        s_op[k] = split ? ss : jobs[k].S;
+        if (split && jobs[k].plan->n_probes > 0) {
+            const prism_smatrix_desc* d = jobs[k].desc;
+            HIP_TRY(timed(PRISM_K_SPLIT, st, [&] {
+                return launch_split_s(precision, static_cast<const float2*>(jobs[k].S), ss, d->n_beams, d->ns, st);
+            }));
+        }
+    }
     for (int k = 0; k < n_jobs; ++k) {
         const prism_probe_job& jb = jobs[k];
         const prism_smatrix_desc* d = jb.desc;
         const prism_probe_plan* plan = jb.plan;
         const char* pb = static_cast<const char*>(jb.plan_dev);
         const int P = (int)plan->n_probes, B = d->n_beams, M = d->m_win;
-        const size_t Pc = (size_t)std::max(P, 1);
-        float2* C = c.take<float2>(Pc * B);
-        float2* win = c.take<float2>(Pc * M * M);
-        float* inten = M > 128 ? c.take<float>(Pc * M * M) : nullptr;
         if (P == 0) continue;
         auto xy = reinterpret_cast<const double2*>(pb + plan->off[0]);
         auto corner = reinterpret_cast<const int2*>(pb + plan->off[1]);
@@ -659,16 +695,18 @@ static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, voi
         auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
         auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
         auto aberr = (plan->C1 != 0.0 || plan->C3 != 0.0) ? reinterpret_cast<const float2*>(pb + plan->off[8]) : nullptr;
+        const double inv_L = 1.0 / d->grid.cell[0];
+        const float amp = (float)(1.0 / std::sqrt((double)B));
         HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
-            return launch_coefficients(C, xy, beams, aberr, P, B, 1.0 / d->grid.cell[0],
-                                       (float)(1.0 / std::sqrt((double)B)), st);
+            return split ? launch_coefficients_split(precision, jd[k].C, xy, beams, aberr, P, B, inv_L, amp, st)
+                         : launch_coefficients(static_cast<float2*>(jd[k].C), xy, beams, aberr, P, B, inv_L, amp, st);
         }));
-        ca.push_back(ContractArgs{C, static_cast<const float2*>(jb.S), win, tstart, tprobes, corner, plan->n_tiles,
+        ca.push_back(ContractArgs{jd[k].C, s_op[k], jd[k].win, tstart, tprobes, corner, plan->n_tiles,
                                   plan->max_per_tile, B, d->ns, M});
         int lg = 0;
         while ((1 << lg) < M) ++lg;
-        wa[lg].push_back(WindowArgs{win, inten, jb.out, jb.diffraction, perm, bstart, tw_m, P, plan->n_bins,
-                                    jb.out_scale, jb.accumulate});
+        wa[lg].push_back(WindowArgs{jd[k].win, jd[k].inten, jb.out, jb.diffraction, perm, bstart, tw_m, P,
+                                    plan->n_bins, jb.out_scale, jb.accumulate});
     }
     if (!ca.empty())
         HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] { return launch_contract_batch(precision, ca.data(), (int)ca.size(), st); }));
@@ -1078,7 +1116,8 @@ int prism_build_smatrix_streaming(const prism_smatrix_desc* d, const float* V_ho
 // --------------------------------------------------- streaming synthesis --
 struct StreamSynthDev {
     float2* Sst[2];
-    float2 *C, *win;
+    void *C, *Ssplit;
+    float2* win;
     float* inten;
 };
 
@@ -1087,7 +1126,8 @@ static void stream_synth_carve(Carve& c, const prism_smatrix_desc* d, const pris
     const size_t P = (size_t)std::max<int64_t>(plan->n_probes, 1), M = d->m_win;
     m.Sst[0] = c.take<float2>((size_t)chunk * d->ns * d->ns);
     m.Sst[1] = c.take<float2>((size_t)chunk * d->ns * d->ns);
-    m.C = c.take<float2>(P * chunk);
+    m.C = c.take<char>(split_c_bytes((int64_t)P, chunk));
+    m.Ssplit = c.take<char>(split_s_bytes(d->ns, chunk));
     m.win = c.take<float2>(P * M * M);
     m.inten = M > 128 ? c.take<float>(P * M * M) : nullptr;
 }
@@ -1136,6 +1176,7 @@ int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_hos
     auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
     auto aberr = (plan->C1 != 0.0 || plan->C3 != 0.0) ? reinterpret_cast<const float2*>(pb + plan->off[8]) : nullptr;
     const float amp = (float)(1.0 / std::sqrt((double)B));
+    const bool split = precision != PRISM_FP32;
     const float2* Sh = static_cast<const float2*>(S_host);
     Ring2 r;
     HIP_TRY(r.init());
@@ -1150,14 +1191,23 @@ int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_hos
                                hipMemcpyHostToDevice, h2d));
         HIP_TRY(hipEventRecord(r.ready[k], h2d));
         HIP_TRY(hipStreamWaitEvent(st, r.ready[k], 0));
+        const double inv_L = 1.0 / d->grid.cell[0];
+        const float2* ab = aberr ? aberr + c0 : nullptr;
+        const void* s_op = m.Sst[k];
+        if (split) {
+            // the slot is free again once its split copy exists
+            HIP_TRY(timed(PRISM_K_SPLIT, st, [&] { return launch_split_s(precision, m.Sst[k], m.Ssplit, nb, d->ns, st); }));
+            HIP_TRY(hipEventRecord(r.freed[k], st));
+            s_op = m.Ssplit;
+        }
         HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
-            return launch_coefficients(m.C, xy, beams + c0, aberr ? aberr + c0 : nullptr, P, nb,
-                                       1.0 / d->grid.cell[0], amp, st);
+            return split ? launch_coefficients_split(precision, m.C, xy, beams + c0, ab, P, nb, inv_L, amp, st)
+                         : launch_coefficients(static_cast<float2*>(m.C), xy, beams + c0, ab, P, nb, inv_L, amp, st);
         }));
-        ContractArgs ca{m.C, m.Sst[k], m.win, tstart, tprobes, corner, plan->n_tiles, plan->max_per_tile, nb, d->ns, M,
+        ContractArgs ca{m.C, s_op, m.win, tstart, tprobes, corner, plan->n_tiles, plan->max_per_tile, nb, d->ns, M,
                         ci > 0 ? 1 : 0};
         HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] { return launch_contract_batch(precision, &ca, 1, st); }));
-        HIP_TRY(hipEventRecord(r.freed[k], st));
+        if (!split) HIP_TRY(hipEventRecord(r.freed[k], st));
         r.used[k] = true;
     }
     WindowArgs wa{m.win, m.inten, out, out4d, perm, bstart, tw_m, P, plan->n_bins, 1.0f, 0};

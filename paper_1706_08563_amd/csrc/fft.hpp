@@ -136,7 +136,12 @@ struct Fft {
     static constexpr int NST = Plan<L>::NST;
     static constexpr int LPT = L / E;                 // lanes per transform (<= 64)
     static_assert(LPT <= 64, "one transform must fit in a wavefront");
-    static constexpr int LDS = L + L / 8;             // padded exchange buffer (float2)
+    // Exchange buffers insert one pad slot every 2^PADSH elements: with 32
+    // four-byte banks serving 16 lanes of a 64-bit access per cycle, this
+    // spreads the strided stage writes and keeps the natural-order reads
+    // nearly conflict-free (one slot every 8 for L <= 64, every 16 above).
+    static constexpr int PADSH = L <= 64 ? 3 : 4;
+    static constexpr int LDS = L + (L >> PADSH);      // padded exchange buffer (float2)
 
     static constexpr int radix(int s) { return Plan<L>::R[s]; }
     static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
@@ -144,7 +149,7 @@ struct Fft {
     static constexpr int tw_off(int s) { return s <= 1 ? 0 : tw_off(s - 1) + (E / radix(s - 1)) * (radix(s - 1) - 1); }
     static constexpr int NTW = tw_off(NST) > 0 ? tw_off(NST) : 1;
 
-    __device__ __forceinline__ static int pad(int i) { return i + (i >> 3); }
+    __device__ __forceinline__ static int pad(int i) { return i + (i >> PADSH); }
 
     // Forward twiddles of this lane, read from W_L[m] = e^{-2 pi i m / L}.
     struct Twiddles {
@@ -169,16 +174,10 @@ struct Fft {
         }
     };
 
-    // LDS accessors of a transform's exchange space: a padded contiguous
-    // buffer (rows), or a strided column of a 2D LDS array.
+    // LDS accessor of a transform's padded exchange buffer.
     struct RowX {
         float2* p;
         __device__ __forceinline__ float2& operator()(int i) const { return p[pad(i)]; }
-    };
-    struct ColX {
-        float2* p;
-        int stride;
-        __device__ __forceinline__ float2& operator()(int i) const { return p[i * stride]; }
     };
 
     template <int DIR, int S, class X>
@@ -293,11 +292,6 @@ struct Fft {
     template <int DIR>
     __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const Twiddles& tw, int lt) {
         stage<DIR, 0>(v, RowX{lds}, tw, lt);
-    }
-    // Same, exchanging through the LDS column p[i * stride], i < L.
-    template <int DIR>
-    __device__ __forceinline__ static void run_col(float2 (&v)[E], float2* p, int stride, const Twiddles& tw, int lt) {
-        stage<DIR, 0>(v, ColX{p, stride}, tw, lt);
     }
 };
 

@@ -57,10 +57,30 @@ hipError_t launch_potential(float* V, int n, int n_slices, double L, const PotAt
 hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, const float2* aberr, int n_probes,
                                int n_beams, double inv_L, float amp, hipStream_t st);
 
+// Operand layouts of the MFMA contraction.  A K step is 16 beams; a record
+// holds, for one (pixel or probe, K step), NP parts (hi, lo) x (re, im) x two
+// halves of 8 beams as bf16: NP * 64 bytes, beams past n_beams zero.
+//   split S:  [tile of 16 x 16 pixels][K step][pixel of the tile][record],
+//             16-byte chunks of a record permuted by the pixel (bank spread)
+//   split C:  [probe][K step][record]
+constexpr int KSTEP = 16;
+inline int ksteps_of(int n_beams) { return (n_beams + KSTEP - 1) / KSTEP; }
+// Bytes reserved for either split layout (the split-BF16 size, the larger).
+inline size_t split_s_bytes(int ns, int n_beams) { return (size_t)ns * ns * ksteps_of(n_beams) * 128; }
+inline size_t split_c_bytes(int64_t n_probes, int n_beams) { return (size_t)n_probes * ksteps_of(n_beams) * 128; }
+// S [n_beams][ns][ns] complex64 -> split S (precision PRISM_SPLIT_BF16X3 or PRISM_BF16).
+hipError_t launch_split_s(int precision, const float2* S, void* Ssplit, int n_beams, int ns, hipStream_t st);
+// Coefficients as launch_coefficients, written as split C.
+hipError_t launch_coefficients_split(int precision, void* Csplit, const double2* xy, const int2* beams,
+                                     const float2* aberr, int n_probes, int n_beams, double inv_L, float amp,
+                                     hipStream_t st);
+
 // Windowed contraction of one probe set: win[p][v][u] = sum_b C[p][b] S[b][pix].
+// C and S are complex64 ([n_probes][n_beams], [n_beams][ns][ns]) for FP32 and
+// the split layouts above for the MFMA precisions.
 struct ContractArgs {
-    const float2* C;
-    const float2* S;
+    const void* C;
+    const void* S;
     float2* win;
     const int* tile_start;
     const int* tile_probes;

@@ -14,6 +14,17 @@ constexpr int WG = 256;
 // ------------------------------------------------------------ coefficients --
 // C[p][b] = amp e^{-2 pi i (kx x + ky y)/L}; the phase argument is formed in
 // FP64 and reduced to [-1/2, 1/2] turns before the FP32 sincos.
+__device__ __forceinline__ float2 coefficient(double2 r, int2 k, const float2* __restrict__ aberr, int b,
+                                              double inv_L, float amp) {
+    double a = ((double)k.x * r.x + (double)k.y * r.y) * inv_L;
+    float fr = (float)(a - rint(a));
+    float s, c;
+    sincosf(-6.283185307179586f * fr, &s, &c);
+    float2 v = make_float2(amp * c, amp * s);
+    if (aberr) v = cmul(v, aberr[b]);
+    return v;
+}
+
 __global__ __launch_bounds__(WG) void k_coefficients(float2* __restrict__ C, const double2* __restrict__ xy,
                                                      const int2* __restrict__ beams,
                                                      const float2* __restrict__ aberr, int n_probes, int n_beams,
@@ -21,15 +32,7 @@ __global__ __launch_bounds__(WG) void k_coefficients(float2* __restrict__ C, con
     int64_t total = (int64_t)n_probes * n_beams;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
         int p = (int)(i / n_beams), b = (int)(i % n_beams);
-        double2 r = xy[p];
-        int2 k = beams[b];
-        double a = ((double)k.x * r.x + (double)k.y * r.y) * inv_L;
-        float fr = (float)(a - rint(a));
-        float s, c;
-        sincosf(-6.283185307179586f * fr, &s, &c);
-        float2 v = make_float2(amp * c, amp * s);
-        if (aberr) v = cmul(v, aberr[b]);
-        C[i] = v;
+        C[i] = coefficient(xy[p], beams[b], aberr, b, inv_L, amp);
     }
 }
 
@@ -55,13 +58,14 @@ constexpr int TILE = 16;
 
 // Work of one (request's) probe synthesis inside a batched contraction launch.
 struct ContractJob {
-    const float2* C;          // [n_probes][n_beams] coefficients
-    const float2* S;          // [n_beams][ns][ns]
+    const void* C;            // coefficients: complex64 [n_probes][n_beams] (FP32) or split C
+    const void* S;            // S-matrix: complex64 [n_beams][ns][ns] (FP32) or split S
     float2* win;              // [n_probes][m][m]
     const int* tile_start;    // [n_tiles + 1]
     const int* tile_probes;
     const int2* corner;       // window corner per probe
     int n_beams, ns, m;
+    int ksteps;               // K steps of 16 beams (split layouts)
     int accumulate;           // 1: add to the windows' contents (beam chunks of one sum)
     int chunks;               // workgroups per tile (probe chunks)
     int n_tiles;
@@ -107,8 +111,8 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
     int tile, chunk;
     ContractJob job;
     if (!locate(batch, job, tile, chunk)) return;
-    const float2* __restrict__ C = job.C;
-    const float2* __restrict__ S = job.S;
+    const float2* __restrict__ C = static_cast<const float2*>(job.C);
+    const float2* __restrict__ S = static_cast<const float2*>(job.S);
     float2* __restrict__ win = job.win;
     const int* __restrict__ tile_probes = job.tile_probes;
     const int2* __restrict__ corner = job.corner;
@@ -178,17 +182,20 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
 // and each product is hi*hi + hi*lo + lo*hi accumulated in FP32 (the lo*lo
 // term, ~2^-16 relative, is dropped).  Plain mode keeps hi*hi only.
 //
-// Workgroup: one 16 x 16 pixel tile x 64 probes.  Wave w owns tile rows
-// 4w..4w+3 (four 16-pixel MFMA column blocks) and all four 16-probe row blocks.
+// Both operands are converted once, before the contraction, into records of
+// 16 beams (see kernels.hpp): S per (pixel tile, K step), C per (probe, K
+// step).  A workgroup (one 16 x 16 pixel tile x 64 probes) then copies each K
+// step's records straight into LDS and feeds the MFMAs; the next K step's
+// global loads are in flight while the current step's MFMAs run.  Wave w owns
+// tile rows 4w..4w+3 (four 16-pixel MFMA column blocks) and all four 16-probe
+// row blocks.
 namespace mfmac {
 constexpr int PC = 64;   // probes per workgroup
-constexpr int KB = 16;   // beams per K step
 }
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
-
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 
 // Two floats to packed bf16 (round to nearest even, v_cvt_pk_bf16_f32).
@@ -204,24 +211,133 @@ __device__ __forceinline__ void split_pair(float a, float b, unsigned int& hi, u
 }
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-template <bool SPLIT>
-__global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
+// Record chunk c (= part * 4 + reim * 2 + half) of row r sits at chunk
+// position c ^ key(r): 8 consecutive rows then touch 8 distinct 16-byte bank
+// groups (records of 128 bytes: key = r & 7; of 64 bytes: two rows share a
+// 128-byte line and key = (r >> 1) & 3).
+template <int NP>
+__device__ __forceinline__ int rec_key(int r) { return NP == 2 ? (r & 7) : ((r >> 1) & 3); }
+
+// Records of 8 complex values v[0..7] (beams half*8 + 0..7): writes chunks
+// (reim, half) of each part into ch[part * 4 + reim * 2 + half].
+template <int NP>
+__device__ __forceinline__ void make_chunks(const float2 (&v)[8], int half, u32x4 (&ch)[NP * 4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        unsigned int rh, rl, ih, il;
+        if constexpr (NP == 2) {
+            split_pair(v[2 * i].x, v[2 * i + 1].x, rh, rl);
+            split_pair(v[2 * i].y, v[2 * i + 1].y, ih, il);
+            ch[4 + half][i] = rl;
+            ch[6 + half][i] = il;
+        } else {
+            rh = pack_bf16(v[2 * i].x, v[2 * i + 1].x);
+            ih = pack_bf16(v[2 * i].y, v[2 * i + 1].y);
+        }
+        ch[half][i] = rh;
+        ch[2 + half][i] = ih;
+    }
+}
+
+// Split S: workgroup = (tile, K step), thread = pixel of the tile.
+template <int NP>
+__global__ __launch_bounds__(WG) void k_split_s(const float2* __restrict__ S, u32x4* __restrict__ out, int n_beams,
+                                                int ns, int K) {
+    constexpr int NCH = NP * 4;
+    const int blk = blockIdx.x, tile = blk / K, k = blk % K;
+    const int ntx = ns / TILE, p = threadIdx.x;
+    const int y = (tile / ntx) * TILE + p / TILE, x = (tile % ntx) * TILE + p % TILE;
+    const size_t plane = (size_t)ns * ns;
+    const float2* src = S + (size_t)y * ns + x;
+    float2 v[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int b = k * KSTEP + h * 8 + j;
+            v[h][j] = b < n_beams ? src[(size_t)b * plane] : make_float2(0.f, 0.f);
+        }
+    u32x4 ch[NCH];
+    make_chunks<NP>(v[0], 0, ch);
+    make_chunks<NP>(v[1], 1, ch);
+    u32x4* rec = out + ((size_t)blk * 256 + p) * NCH;
+    const int key = rec_key<NP>(p);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) rec[c ^ key] = ch[c];
+}
+
+// Split C: thread = (probe, K step, half of 8 beams); records unpermuted.
+template <int NP>
+__global__ __launch_bounds__(WG) void k_coefficients_split(u32x4* __restrict__ Cs, const double2* __restrict__ xy,
+                                                           const int2* __restrict__ beams,
+                                                           const float2* __restrict__ aberr, int n_probes,
+                                                           int n_beams, int K, double inv_L, float amp) {
+    constexpr int NCH = NP * 4;
+    const int64_t total = (int64_t)n_probes * K * 2;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
+        const int p = (int)(i / (2 * K)), r = (int)(i % (2 * K)), k = r >> 1, half = r & 1;
+        const double2 xyp = xy[p];
+        float2 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int b = k * KSTEP + half * 8 + j;
+            v[j] = b < n_beams ? coefficient(xyp, beams[b], aberr, b, inv_L, amp) : make_float2(0.f, 0.f);
+        }
+        u32x4 ch[NCH];
+        make_chunks<NP>(v, half, ch);
+        u32x4* rec = Cs + ((size_t)p * K + k) * NCH;
+#pragma unroll
+        for (int part = 0; part < NP; ++part) {
+            rec[part * 4 + half] = ch[part * 4 + half];
+            rec[part * 4 + 2 + half] = ch[part * 4 + 2 + half];
+        }
+    }
+}
+
+hipError_t launch_split_s(int precision, const float2* S, void* Ssplit, int n_beams, int ns, hipStream_t st) {
+    const int K = ksteps_of(n_beams), ntx = ns / TILE;
+    dim3 grid((unsigned)(ntx * ntx * K));
+    if (precision == 1)
+        hipLaunchKernelGGL(k_split_s<2>, grid, dim3(WG), 0, st, S, static_cast<u32x4*>(Ssplit), n_beams, ns, K);
+    else
+        hipLaunchKernelGGL(k_split_s<1>, grid, dim3(WG), 0, st, S, static_cast<u32x4*>(Ssplit), n_beams, ns, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_coefficients_split(int precision, void* Csplit, const double2* xy, const int2* beams,
+                                     const float2* aberr, int n_probes, int n_beams, double inv_L, float amp,
+                                     hipStream_t st) {
+    const int K = ksteps_of(n_beams);
+    int64_t total = (int64_t)n_probes * K * 2;
+    int64_t blocks = (total + WG - 1) / WG;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    u32x4* Cs = static_cast<u32x4*>(Csplit);
+    if (precision == 1)
+        hipLaunchKernelGGL(k_coefficients_split<2>, dim3((unsigned)blocks), dim3(WG), 0, st, Cs, xy, beams, aberr,
+                           n_probes, n_beams, K, inv_L, amp);
+    else
+        hipLaunchKernelGGL(k_coefficients_split<1>, dim3((unsigned)blocks), dim3(WG), 0, st, Cs, xy, beams, aberr,
+                           n_probes, n_beams, K, inv_L, amp);
+    return hipGetLastError();
+}
+
+template <int NP>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_contract_mfma(ContractBatch batch) {
     using namespace mfmac;
-    constexpr int NP = SPLIT ? 2 : 1;           // hi (, lo)
-    // [part][re/im][row][beam]: the 16 beams of a row are contiguous (32 B)
-    __shared__ __attribute__((aligned(16))) u32x4 Ss[NP][2][256][2];
-    __shared__ __attribute__((aligned(16))) uint2 Cs[NP][2][PC][4];
+    constexpr int NCH = NP * 4;                 // 16-byte chunks per record
+    constexpr int CPT = PC * NCH / WG;          // C chunks staged per thread
+    __shared__ u32x4 Ss[256 * NCH];             // one K step of the tile (records as stored)
+    __shared__ u32x4 Cl[PC * NCH];              // one K step of the probe chunk (records permuted)
     __shared__ int pidx[PC];
 
     int tile, chunk;
     ContractJob job;
     if (!locate(batch, job, tile, chunk)) return;
-    const float2* __restrict__ C = job.C;
-    const float2* __restrict__ S = job.S;
     float2* __restrict__ win = job.win;
     const int* __restrict__ tile_probes = job.tile_probes;
     const int2* __restrict__ corner = job.corner;
-    const int n_beams = job.n_beams, ns = job.ns, m = job.m;
+    const int ns = job.ns, m = job.m, K = job.ksteps;
     const int t0 = job.tile_start[tile], t1 = job.tile_start[tile + 1];
     const int pc0 = t0 + chunk * PC;
     if (pc0 >= t1) return;
@@ -239,101 +355,55 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
             accr[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
             acci[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-    const size_t plane = (size_t)ns * ns;
-    // S staging: thread = one tile pixel, 16 beams per K step
-    const int spix = tid;
-    const float2* Sp = S + (size_t)(ty0 + spix / TILE) * ns + tx0 + (spix % TILE);
-    // C staging: thread = (probe, 4 beams)
-    const int cp = tid >> 2, cb = (tid & 3) * 4;
+    const u32x4* __restrict__ Sg = static_cast<const u32x4*>(job.S) + (size_t)tile * K * 256 * NCH + tid;
     __syncthreads();
-    const int cq = pidx[cp];
-    const float2* Cp = C + (size_t)(cq < 0 ? 0 : cq) * n_beams + cb;
+    // C staging: chunk q = tid * CPT + j of the step's PC x NCH chunks
+    const int crow = (tid * CPT) / NCH, cc0 = (tid * CPT) % NCH;
+    const int cq = pidx[crow];
+    const u32x4* __restrict__ Cg = static_cast<const u32x4*>(job.C) + (size_t)(cq < 0 ? 0 : cq) * K * NCH + cc0;
+    const int ckey = rec_key<NP>(crow);
+    const u32x4 zero = u32x4{0u, 0u, 0u, 0u};
 
-    float2 sv[KB], cv[4];
-    auto load = [&](int b0) {
+    u32x4 sreg[NCH], creg[CPT];
 #pragma unroll
-        for (int k = 0; k < KB; ++k)
-            sv[k] = (b0 + k < n_beams) ? Sp[(size_t)(b0 + k) * plane] : make_float2(0.f, 0.f);
+    for (int j = 0; j < NCH; ++j) sreg[j] = Sg[j * 256];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            cv[k] = (cq >= 0 && b0 + cb + k < n_beams) ? Cp[b0 + k] : make_float2(0.f, 0.f);
-    };
-    load(0);
+    for (int j = 0; j < CPT; ++j) creg[j] = cq >= 0 ? Cg[j] : zero;
 
     const int col = lane & 15, g = lane >> 4;   // MFMA operand lane roles
-    for (int b0 = 0; b0 < n_beams; b0 += KB) {
-        // ---- convert and stage this K step (16 B stores)
-        {
-            unsigned int rh[KB / 2], ih[KB / 2], rl[KB / 2], il[KB / 2];
+    const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int k = 0; k < KB / 2; ++k) {
-                if constexpr (SPLIT) {
-                    split_pair(sv[2 * k].x, sv[2 * k + 1].x, rh[k], rl[k]);
-                    split_pair(sv[2 * k].y, sv[2 * k + 1].y, ih[k], il[k]);
-                } else {
-                    rh[k] = pack_bf16(sv[2 * k].x, sv[2 * k + 1].x);
-                    ih[k] = pack_bf16(sv[2 * k].y, sv[2 * k + 1].y);
-                }
-            }
-            Ss[0][0][spix][0] = u32x4{rh[0], rh[1], rh[2], rh[3]};
-            Ss[0][0][spix][1] = u32x4{rh[4], rh[5], rh[6], rh[7]};
-            Ss[0][1][spix][0] = u32x4{ih[0], ih[1], ih[2], ih[3]};
-            Ss[0][1][spix][1] = u32x4{ih[4], ih[5], ih[6], ih[7]};
-            if constexpr (SPLIT) {
-                Ss[NP - 1][0][spix][0] = u32x4{rl[0], rl[1], rl[2], rl[3]};
-                Ss[NP - 1][0][spix][1] = u32x4{rl[4], rl[5], rl[6], rl[7]};
-                Ss[NP - 1][1][spix][0] = u32x4{il[0], il[1], il[2], il[3]};
-                Ss[NP - 1][1][spix][1] = u32x4{il[4], il[5], il[6], il[7]};
-            }
-            unsigned int crh[2], cih[2], crl[2], cil[2];
+        for (int j = 0; j < NCH; ++j) Ss[tid + j * 256] = sreg[j];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if constexpr (SPLIT) {
-                    split_pair(cv[2 * k].x, cv[2 * k + 1].x, crh[k], crl[k]);
-                    split_pair(cv[2 * k].y, cv[2 * k + 1].y, cih[k], cil[k]);
-                } else {
-                    crh[k] = pack_bf16(cv[2 * k].x, cv[2 * k + 1].x);
-                    cih[k] = pack_bf16(cv[2 * k].y, cv[2 * k + 1].y);
-                }
-            }
-            Cs[0][0][cp][cb / 4] = make_uint2(crh[0], crh[1]);
-            Cs[0][1][cp][cb / 4] = make_uint2(cih[0], cih[1]);
-            if constexpr (SPLIT) {
-                Cs[NP - 1][0][cp][cb / 4] = make_uint2(crl[0], crl[1]);
-                Cs[NP - 1][1][cp][cb / 4] = make_uint2(cil[0], cil[1]);
-            }
-        }
+        for (int j = 0; j < CPT; ++j) Cl[crow * NCH + ((cc0 + j) ^ ckey)] = creg[j];
         __syncthreads();
-        // ---- next K step's global loads fly while this step's MFMAs run
-        if (b0 + KB < n_beams) load(b0 + KB);
-        // ---- B operands: pixel block pb = tile row 4*wave + pb, lane column = pixel
-        //      k-group g: 0,1 -> Sr beams 8g.., 2,3 -> Si beams 8(g-2)..
+        if (k + 1 < K) {
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) sreg[j] = Sg[(size_t)(k + 1) * 256 * NCH + j * 256];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) creg[j] = cq >= 0 ? Cg[(size_t)(k + 1) * NCH + j] : zero;
+        }
+        // B operand of lane group g: chunk part*4 + g (re beams 0-7, 8-15, im beams 0-7, 8-15)
         u32x4 Bop[NP][4];
 #pragma unroll
-        for (int part = 0; part < NP; ++part)
+        for (int pb = 0; pb < 4; ++pb) {
+            const int pix = (4 * wave + pb) * TILE + col;
+            const int key = rec_key<NP>(pix);
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb) {
-                const int pix = (4 * wave + pb) * TILE + col;
-                Bop[part][pb] = Ss[part][g >> 1][pix][g & 1];
-            }
+            for (int part = 0; part < NP; ++part) Bop[part][pb] = Ss[pix * NCH + ((part * 4 + g) ^ key)];
+        }
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb) {
-            const int prow = 16 * qb + col;
-            // A_r = [Cr | -Ci], A_i = [Ci | Cr]
+            const int row = 16 * qb + col;
+            const int key = rec_key<NP>(row);
+            // A_r = [Cr | -Ci]: chunk part*4 + g, negated for g >= 2; A_i = [Ci | Cr]: chunk part*4 + (g ^ 2)
             u32x4 Ar[NP], Ai[NP];
 #pragma unroll
             for (int part = 0; part < NP; ++part) {
-                const uint2* cr2 = &Cs[part][0][prow][2 * (g & 1)];
-                const uint2* ci2 = &Cs[part][1][prow][2 * (g & 1)];
-                u32x4 cr = u32x4{cr2[0].x, cr2[0].y, cr2[1].x, cr2[1].y};
-                u32x4 ci = u32x4{ci2[0].x, ci2[0].y, ci2[1].x, ci2[1].y};
-                if (g < 2) {
-                    Ar[part] = cr;
-                    Ai[part] = ci;
-                } else {
-                    Ar[part] = ci ^ u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-                    Ai[part] = cr;
-                }
+                Ar[part] = Cl[row * NCH + ((part * 4 + g) ^ key)];
+                if (g >= 2) Ar[part] ^= sgn;
+                Ai[part] = Cl[row * NCH + ((part * 4 + (g ^ 2)) ^ key)];
             }
 #pragma unroll
             for (int pb = 0; pb < 4; ++pb) {
@@ -341,7 +411,7 @@ __global__ __launch_bounds__(WG) void k_contract_mfma(ContractBatch batch) {
                                                                       accr[qb][pb], 0, 0, 0);
                 acci[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ai[0]), as_bf16x8(Bop[0][pb]),
                                                                       acci[qb][pb], 0, 0, 0);
-                if constexpr (SPLIT) {
+                if constexpr (NP == 2) {
                     accr[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ar[0]), as_bf16x8(Bop[1][pb]),
                                                                           accr[qb][pb], 0, 0, 0);
                     acci[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ai[0]), as_bf16x8(Bop[1][pb]),
@@ -396,6 +466,7 @@ hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_
             job.n_beams = a.n_beams;
             job.ns = a.ns;
             job.m = a.m;
+            job.ksteps = ksteps_of(a.n_beams);
             job.accumulate = a.accumulate;
             job.chunks = (a.max_per_tile + pc - 1) / pc;
             if (job.chunks < 1) job.chunks = 1;
@@ -409,9 +480,9 @@ hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_
         if (precision == 0)
             hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, b);
         else if (precision == 1)
-            hipLaunchKernelGGL(k_contract_mfma<true>, grid, dim3(WG), 0, st, b);
+            hipLaunchKernelGGL(k_contract_mfma<2>, grid, dim3(WG), 0, st, b);
         else
-            hipLaunchKernelGGL(k_contract_mfma<false>, grid, dim3(WG), 0, st, b);
+            hipLaunchKernelGGL(k_contract_mfma<1>, grid, dim3(WG), 0, st, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -445,11 +516,16 @@ struct WindowBatch {
     WindowJob job[MAX_JOBS];
 };
 
+// The window sits unpadded in LDS with row stride M + 16/LPT, so that the
+// strided column reads of the 16 lanes of a 64-bit access (16/LPT columns of
+// LPT lanes each) fall in distinct banks; the transforms exchange through a
+// private padded buffer per transform instead of the window itself.
 template <int M>
 __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
     using F = Fft<M>;
-    constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, ROW = F::LDS + 1;
+    constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, ROW = M + 16 / LPT;
     __shared__ float2 buf[M * ROW];
+    __shared__ float2 xch[4 * G * F::LDS];
     int jj = 0;
 #pragma unroll
     for (int k = 1; k < MAX_JOBS; ++k)
@@ -481,48 +557,47 @@ __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
 #pragma unroll
             for (int k = 0; k < BATCH; ++k) {
                 const int idx = tid + (k0 + k) * WG;
-                if (idx < M * M) buf[(idx / M) * ROW + F::pad(idx % M)] = ld[k];
+                if (idx < M * M) buf[(idx / M) * ROW + idx % M] = ld[k];
             }
         }
     }
     __syncthreads();
     typename F::Twiddles tw;
     tw.load(tw_m, lt);
+    float2* const x = xch + (wave * G + g) * F::LDS;
     // rows
     for (int r0 = wave * G; r0 < M; r0 += 4 * G) {
         float2* row = buf + (r0 + g) * ROW;
         float2 v[E];
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = row[F::pad(lt + LPT * i)];
-        F::template run<-1>(v, row, tw, lt);
-        wave_sync();
+        for (int i = 0; i < E; ++i) v[i] = row[lt + LPT * i];
+        F::template run<-1>(v, x, tw, lt);
 #pragma unroll
-        for (int i = 0; i < E; ++i) row[F::pad(lt + LPT * i)] = v[i];
+        for (int i = 0; i < E; ++i) row[lt + LPT * i] = v[i];
     }
     __syncthreads();
     // columns, then intensity in place
     const float scale = 1.0f / ((float)M * (float)M * (float)M * (float)M);
     for (int c0 = wave * G; c0 < M; c0 += 4 * G) {
-        float2* col = buf + F::pad(c0 + g);
+        float2* col = buf + c0 + g;
         float2 v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = col[(lt + LPT * i) * ROW];
-        F::template run_col<-1>(v, col, ROW, tw, lt);
-        wave_sync();
+        F::template run<-1>(v, x, tw, lt);
 #pragma unroll
         for (int i = 0; i < E; ++i) col[(lt + LPT * i) * ROW] = make_float2(cnorm(v[i]) * scale, 0.f);
     }
     __syncthreads();
     if (diff) {
         float* d = diff + (size_t)p * M * M;
-        for (int idx = tid; idx < M * M; idx += WG) d[idx] = buf[(idx / M) * ROW + F::pad(idx % M)].x;
+        for (int idx = tid; idx < M * M; idx += WG) d[idx] = buf[(idx / M) * ROW + idx % M].x;
     }
     if (!out) return;
     for (int b = wave; b < n_bins; b += 4) {
         float s = 0.f;
         for (int k = bin_start[b] + lane; k < bin_start[b + 1]; k += 64) {
             int pix = perm[k];
-            s += buf[(pix / M) * ROW + F::pad(pix % M)].x;
+            s += buf[(pix / M) * ROW + pix % M].x;
         }
         s = wave_sum(s);
         if (lane == 0) {
@@ -583,6 +658,7 @@ __global__ __launch_bounds__(WG) void k_window_cols(const float2* __restrict__ w
     using F = Fft<M>;
     constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, CW = 16, ROWS = CW + 1;
     __shared__ float2 strip[M * ROWS];
+    __shared__ float2 xch[4 * G * F::LDS];
     const int p = blockIdx.y, u0 = blockIdx.x * CW;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane / LPT, lt = lane % LPT;
@@ -612,7 +688,7 @@ __global__ __launch_bounds__(WG) void k_window_cols(const float2* __restrict__ w
         float2 v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = col[(lt + LPT * i) * ROWS];
-        F::template run_col<-1>(v, col, ROWS, tw, lt);
+        F::template run<-1>(v, xch + (wave * G + g) * F::LDS, tw, lt);
 #pragma unroll
         for (int i = 0; i < E; ++i) I[(size_t)(lt + LPT * i) * M + u0 + c] = cnorm(v[i]) * scale;
     }

@@ -40,8 +40,11 @@ constexpr int WG = 256;      // 4 wavefronts
 #ifndef PRISM_PASSB_WPE
 #define PRISM_PASSB_WPE 1
 #endif
+#ifndef PRISM_PASSA_TPREF
+#define PRISM_PASSA_TPREF 1      // 1: transmission row requested before the inverse row transforms
+#endif
 #ifndef PRISM_PASSB_COLS
-#define PRISM_PASSB_COLS 4       // adjacent columns per transform group in pass B (pipelined loads)
+#define PRISM_PASSB_COLS 8       // adjacent columns per transform group in pass B (pipelined loads)
 #endif
 
 // Columns per pass-B transform group: pipelined when the column count allows.
@@ -139,8 +142,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
         // transmission of this row, requested before the inverse transforms
         // so the load latency hides behind them
         float4 trow[E];
-        {
-            const float4* Trow = reinterpret_cast<const float4*>(T + (size_t)y * N);
+        const float4* Trow = reinterpret_cast<const float4*>(T + (size_t)y * N);
+        if constexpr (PRISM_PASSA_TPREF) {
 #pragma unroll
             for (int i = 0; i < E; ++i) trow[i] = Trow[lt + LPT * i];
         }
@@ -168,6 +171,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
                 F::template run<+1>(e, row, tw, lt);
                 F::template run<+1>(o, row, tw, lt);
             }
+        }
+        if constexpr (!PRISM_PASSA_TPREF) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) trow[i] = Trow[lt + LPT * i];
         }
 #pragma unroll
         for (int i = 0; i < E; ++i) {
