@@ -301,6 +301,22 @@ int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_hos
                                   int32_t precision, int32_t beam_chunk, float* out, float* out4d,
                                   void* ws, size_t ws_bytes, void* stream, void* h2d_stream);
 
+/* Device workspace of prism_probe_outputs_chunked with beam_chunk beams per
+ * chunk (coefficients and split S of one chunk, the windows of all probes). */
+int prism_probe_chunked_workspace(const prism_smatrix_desc* d, const prism_probe_plan* plan,
+                                  int32_t beam_chunk, size_t* bytes);
+
+/* prism_probe_outputs (out, or the 4D output out4d when out is NULL) with S in
+ * device memory, contracted beam_chunk beams at a time into FP32 windows:
+ * the MFMA precisions then need a split copy of one chunk of S instead of
+ * all of it (workspace for S-matrices too large to duplicate).  The result
+ * equals prism_probe_outputs_streaming's for the same chunk size.  Fully
+ * asynchronous.  Errors: PRISM_E_INVAL, PRISM_E_WORKSPACE, PRISM_E_DEVICE. */
+int prism_probe_outputs_chunked(const prism_smatrix_desc* d, const void* S,
+                                const prism_probe_plan* plan, const void* plan_dev,
+                                int32_t precision, int32_t beam_chunk, float* out, float* out4d,
+                                void* ws, size_t ws_bytes, void* stream);
+
 /* Device workspace of multislice_outputs_streaming. */
 int multislice_streaming_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes,
                                    size_t* bytes);

@@ -97,6 +97,10 @@ _SIGNATURES = {
     "prism_probe_outputs_streaming": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p,
                                        c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
                                        c_void_p], c_int32),
+    "prism_probe_chunked_workspace": ([POINTER(prism_smatrix_desc), POINTER(prism_probe_plan), c_int32,
+                                       POINTER(c_size_t)], c_int32),
+    "prism_probe_outputs_chunked": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p,
+                                     c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "multislice_streaming_workspace": ([POINTER(prism_grid), c_int32, c_int64, POINTER(c_size_t)], c_int32),
     "multislice_outputs_streaming": ([POINTER(prism_grid), c_double, c_double, POINTER(prism_aberrations), c_void_p,
                                       c_void_p, c_int64, c_double, c_int32, c_int32, c_void_p, c_void_p, c_size_t,
@@ -114,6 +118,16 @@ EXPORTED = tuple(_SIGNATURES)
 
 
 def load():
+    # The library and PyTorch must share one HIP runtime (streams and device
+    # memory cross between them).  PyTorch's HIP libraries find their runtime
+    # under an unversioned name next to themselves; loading this library
+    # first would bind the system runtime to the versioned name and leave
+    # PyTorch to load a second copy.  Import torch first so that this
+    # library binds to the runtime PyTorch already loaded.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
                           " (hipcc --offload-arch=gfx950)")

@@ -284,6 +284,29 @@ def prism_probe_outputs_streaming(d: prism_smatrix_desc, S_host, plan: ProbePlan
     return out
 
 
+def prism_probe_chunked_workspace(d: prism_smatrix_desc, plan: ProbePlan, beam_chunk: int) -> int:
+    need = ctypes.c_size_t()
+    check(lib.prism_probe_chunked_workspace(ctypes.byref(d), ctypes.byref(plan.plan), int(beam_chunk),
+                                            ctypes.byref(need)))
+    return need.value
+
+
+def prism_probe_outputs_chunked(d: prism_smatrix_desc, S, plan: ProbePlan, precision: int = PRISM_FP32,
+                                beam_chunk: int = 128, ws=None, out=None, diffraction: bool = False):
+    """Probe outputs (or the 4D output) from a device S-matrix contracted in beam chunks."""
+    torch = _torch()
+    p = plan.plan
+    if out is None:
+        shape = (p.n_probes, d.m_win, d.m_win) if diffraction else (p.n_probes, p.n_bins)
+        out = torch.empty(shape, dtype=torch.float32, device=S.device)
+    if ws is None:
+        ws = _workspace(prism_probe_chunked_workspace(d, plan, beam_chunk), S.device)
+    o3, o4 = (None, _dev(out)) if diffraction else (_dev(out), None)
+    check(lib.prism_probe_outputs_chunked(ctypes.byref(d), _dev(S), ctypes.byref(p), _dev(plan.dev), int(precision),
+                                          int(beam_chunk), o3, o4, _dev(ws), ws.numel(), _stream()))
+    return out
+
+
 def multislice_streaming_workspace(grid: prism_grid, batch: int, n_probes: int) -> int:
     need = ctypes.c_size_t()
     check(lib.multislice_streaming_workspace(ctypes.byref(grid), int(batch), int(n_probes), ctypes.byref(need)))

@@ -1121,48 +1121,53 @@ struct StreamSynthDev {
     float* inten;
 };
 
+// Beam-chunked synthesis layout: two chunk slots when S is streamed from
+// host memory (none when S is device-resident), the coefficients and split S
+// of one chunk, the windows of all probes.
 static void stream_synth_carve(Carve& c, const prism_smatrix_desc* d, const prism_probe_plan* plan, int chunk,
-                               StreamSynthDev& m) {
+                               bool slots, StreamSynthDev& m) {
     const size_t P = (size_t)std::max<int64_t>(plan->n_probes, 1), M = d->m_win;
-    m.Sst[0] = c.take<float2>((size_t)chunk * d->ns * d->ns);
-    m.Sst[1] = c.take<float2>((size_t)chunk * d->ns * d->ns);
+    m.Sst[0] = slots ? c.take<float2>((size_t)chunk * d->ns * d->ns) : nullptr;
+    m.Sst[1] = slots ? c.take<float2>((size_t)chunk * d->ns * d->ns) : nullptr;
     m.C = c.take<char>(split_c_bytes((int64_t)P, chunk));
     m.Ssplit = c.take<char>(split_s_bytes(d->ns, chunk));
     m.win = c.take<float2>(P * M * M);
     m.inten = M > 128 ? c.take<float>(P * M * M) : nullptr;
 }
 
-int prism_probe_streaming_workspace(const prism_smatrix_desc* d, const prism_probe_plan* plan, int32_t beam_chunk,
-                                    size_t* bytes) {
+static int chunked_ws(const prism_smatrix_desc* d, const prism_probe_plan* plan, int32_t beam_chunk, bool slots,
+                      size_t* bytes) {
     int rc = check_desc(d);
     if (rc) return rc;
     if (!plan || !bytes || beam_chunk < 1 || beam_chunk > d->n_beams)
-        return fail(PRISM_E_INVAL, "streaming synthesis workspace: invalid argument (beam_chunk in [1, %d])",
+        return fail(PRISM_E_INVAL, "chunked synthesis workspace: invalid argument (beam_chunk in [1, %d])",
                     d->n_beams);
     Carve c(nullptr);
     StreamSynthDev m;
-    stream_synth_carve(c, d, plan, beam_chunk, m);
+    stream_synth_carve(c, d, plan, beam_chunk, slots, m);
     *bytes = c.off + 256;
     return PRISM_OK;
 }
 
-int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_host, const prism_probe_plan* plan,
-                                  const void* plan_dev, int32_t precision, int32_t beam_chunk, float* out,
-                                  float* out4d, void* ws, size_t ws_bytes, void* stream, void* h2d_stream) {
+// Probe synthesis over beam chunks accumulated in the FP32 windows.  With
+// h2d set, S is host memory and each chunk is first copied into one of two
+// device slots (one chunk ahead); otherwise S is device memory read in place.
+static int synth_chunked(const prism_smatrix_desc* d, const void* S, const prism_probe_plan* plan,
+                         const void* plan_dev, int32_t precision, int32_t beam_chunk, float* out, float* out4d,
+                         void* ws, size_t ws_bytes, hipStream_t st, hipStream_t h2d, bool streamed) {
     size_t need = 0;
-    int rc = prism_probe_streaming_workspace(d, plan, beam_chunk, &need);
+    int rc = chunked_ws(d, plan, beam_chunk, streamed, &need);
     if (rc) return rc;
     if (precision != PRISM_FP32 && precision != PRISM_SPLIT_BF16X3 && precision != PRISM_BF16)
-        return fail(PRISM_E_INVAL, "streaming synthesis: unknown precision %d", precision);
-    if (!S_host || !plan_dev || (!out && !out4d && plan->n_probes > 0))
-        return fail(PRISM_E_INVAL, "streaming synthesis: NULL argument");
+        return fail(PRISM_E_INVAL, "chunked synthesis: unknown precision %d", precision);
+    if (!S || !plan_dev || (!out && !out4d && plan->n_probes > 0))
+        return fail(PRISM_E_INVAL, "chunked synthesis: NULL argument");
     if (!ws || ws_bytes < need)
-        return fail(PRISM_E_WORKSPACE, "streaming synthesis: workspace %zu < %zu bytes", ws_bytes, need);
+        return fail(PRISM_E_WORKSPACE, "chunked synthesis: workspace %zu < %zu bytes", ws_bytes, need);
     if (plan->n_probes == 0) return PRISM_OK;
-    hipStream_t st = as_stream(stream), h2d = as_stream(h2d_stream);
     Carve c(ws);
     StreamSynthDev m;
-    stream_synth_carve(c, d, plan, beam_chunk, m);
+    stream_synth_carve(c, d, plan, beam_chunk, streamed, m);
     const char* pb = static_cast<const char*>(plan_dev);
     const int P = (int)plan->n_probes, B = d->n_beams, M = d->m_win;
     const size_t layer = (size_t)d->ns * d->ns;
@@ -1177,29 +1182,34 @@ int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_hos
     auto aberr = (plan->C1 != 0.0 || plan->C3 != 0.0) ? reinterpret_cast<const float2*>(pb + plan->off[8]) : nullptr;
     const float amp = (float)(1.0 / std::sqrt((double)B));
     const bool split = precision != PRISM_FP32;
-    const float2* Sh = static_cast<const float2*>(S_host);
+    const double inv_L = 1.0 / d->grid.cell[0];
+    const float2* Sb = static_cast<const float2*>(S);
     Ring2 r;
-    HIP_TRY(r.init());
-    rc = order_after(h2d, st);
-    if (rc) return rc;
+    if (streamed) {
+        HIP_TRY(r.init());
+        rc = order_after(h2d, st);
+        if (rc) return rc;
+    }
     int ci = 0;
     for (int c0 = 0; c0 < B; c0 += beam_chunk, ++ci) {
         const int nb = std::min(beam_chunk, B - c0);
         const int k = ci & 1;
-        if (r.used[k]) HIP_TRY(hipStreamWaitEvent(h2d, r.freed[k], 0));
-        HIP_TRY(hipMemcpyAsync(m.Sst[k], Sh + (size_t)c0 * layer, (size_t)nb * layer * sizeof(float2),
-                               hipMemcpyHostToDevice, h2d));
-        HIP_TRY(hipEventRecord(r.ready[k], h2d));
-        HIP_TRY(hipStreamWaitEvent(st, r.ready[k], 0));
-        const double inv_L = 1.0 / d->grid.cell[0];
+        const float2* chunk = Sb + (size_t)c0 * layer;
+        if (streamed) {
+            if (r.used[k]) HIP_TRY(hipStreamWaitEvent(h2d, r.freed[k], 0));
+            HIP_TRY(hipMemcpyAsync(m.Sst[k], chunk, (size_t)nb * layer * sizeof(float2), hipMemcpyHostToDevice, h2d));
+            HIP_TRY(hipEventRecord(r.ready[k], h2d));
+            HIP_TRY(hipStreamWaitEvent(st, r.ready[k], 0));
+            chunk = m.Sst[k];
+        }
         const float2* ab = aberr ? aberr + c0 : nullptr;
-        const void* s_op = m.Sst[k];
+        const void* s_op = chunk;
         if (split) {
-            // the slot is free again once its split copy exists
-            HIP_TRY(timed(PRISM_K_SPLIT, st, [&] { return launch_split_s(precision, m.Sst[k], m.Ssplit, nb, d->ns, st); }));
-            HIP_TRY(hipEventRecord(r.freed[k], st));
+            HIP_TRY(timed(PRISM_K_SPLIT, st, [&] { return launch_split_s(precision, chunk, m.Ssplit, nb, d->ns, st); }));
             s_op = m.Ssplit;
         }
+        // a streamed slot is free again once its chunk has been read
+        if (streamed && split) HIP_TRY(hipEventRecord(r.freed[k], st));
         HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
             return split ? launch_coefficients_split(precision, m.C, xy, beams + c0, ab, P, nb, inv_L, amp, st)
                          : launch_coefficients(static_cast<float2*>(m.C), xy, beams + c0, ab, P, nb, inv_L, amp, st);
@@ -1207,12 +1217,36 @@ int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_hos
         ContractArgs ca{m.C, s_op, m.win, tstart, tprobes, corner, plan->n_tiles, plan->max_per_tile, nb, d->ns, M,
                         ci > 0 ? 1 : 0};
         HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] { return launch_contract_batch(precision, &ca, 1, st); }));
-        if (!split) HIP_TRY(hipEventRecord(r.freed[k], st));
-        r.used[k] = true;
+        if (streamed && !split) HIP_TRY(hipEventRecord(r.freed[k], st));
+        if (streamed) r.used[k] = true;
     }
     WindowArgs wa{m.win, m.inten, out, out4d, perm, bstart, tw_m, P, plan->n_bins, 1.0f, 0};
     HIP_TRY(timed(PRISM_K_WINDOW, st, [&] { return launch_window_batch(M, &wa, 1, st); }));
     return PRISM_OK;
+}
+
+int prism_probe_streaming_workspace(const prism_smatrix_desc* d, const prism_probe_plan* plan, int32_t beam_chunk,
+                                    size_t* bytes) {
+    return chunked_ws(d, plan, beam_chunk, true, bytes);
+}
+
+int prism_probe_outputs_streaming(const prism_smatrix_desc* d, const void* S_host, const prism_probe_plan* plan,
+                                  const void* plan_dev, int32_t precision, int32_t beam_chunk, float* out,
+                                  float* out4d, void* ws, size_t ws_bytes, void* stream, void* h2d_stream) {
+    return synth_chunked(d, S_host, plan, plan_dev, precision, beam_chunk, out, out4d, ws, ws_bytes,
+                         as_stream(stream), as_stream(h2d_stream), true);
+}
+
+int prism_probe_chunked_workspace(const prism_smatrix_desc* d, const prism_probe_plan* plan, int32_t beam_chunk,
+                                  size_t* bytes) {
+    return chunked_ws(d, plan, beam_chunk, false, bytes);
+}
+
+int prism_probe_outputs_chunked(const prism_smatrix_desc* d, const void* S, const prism_probe_plan* plan,
+                                const void* plan_dev, int32_t precision, int32_t beam_chunk, float* out, float* out4d,
+                                void* ws, size_t ws_bytes, void* stream) {
+    return synth_chunked(d, S, plan, plan_dev, precision, beam_chunk, out, out4d, ws, ws_bytes, as_stream(stream),
+                         nullptr, false);
 }
 
 int prism_timing_enable(int32_t enable) {

@@ -179,7 +179,8 @@ class Scheduler:
 class GpuExecutor:
     """Runs requests with libprism on the current HIP device."""
 
-    def __init__(self, precision: int, probe_chunk_bytes: int = 1 << 30, build_ws_bytes: int = 16 << 30):
+    def __init__(self, precision: int, probe_chunk_bytes: int = 1 << 30, build_ws_bytes: int = 16 << 30,
+                 split_limit_bytes: int = 8 << 30):
         import torch
 
         from . import api
@@ -189,6 +190,9 @@ class GpuExecutor:
         self.precision = precision
         self.probe_chunk_bytes = probe_chunk_bytes
         self.build_ws_bytes = build_ws_bytes
+        # S-matrices whose split copy would exceed this are contracted in beam
+        # chunks (prism_probe_outputs_chunked) instead of in the shared batch
+        self.split_limit_bytes = split_limit_bytes
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
 
@@ -212,10 +216,18 @@ class GpuExecutor:
         chunks = [xy[i:i + pc] for i in range(0, len(xy), pc)]
         plans = [api.prism_probe_plan_init(d, c, req.dalpha) for c in chunks]
         n_bins = plans[0].n_bins
+        kb = (d.n_beams + 15) // 16
+        split_bytes = d.ns * d.ns * kb * 128
+        beam_chunk = 0
+        if split_bytes > self.split_limit_bytes:
+            beam_chunk = max(16, (self.split_limit_bytes // (d.ns * d.ns * 128)) * 16)
+            ws = max(_chunked_ws(d, p, beam_chunk) for p in plans)
+        else:
+            ws = max(p.ws_bytes for p in plans)
         foot = (g.n_slices * g.n * g.n * 4 + d.smatrix_bytes + d.build_ws_bytes
-                + sum(p.plan_bytes for p in plans) + max(p.ws_bytes for p in plans) + len(xy) * n_bins * 4)
+                + sum(p.plan_bytes for p in plans) + ws + len(xy) * n_bins * 4)
         req.info.update(grid=g, desc=d, chunks=chunks, n_bins=n_bins, n_beams=d.n_beams, m_win=d.m_win,
-                        beam_batch=d.beam_batch or d.n_beams)
+                        beam_batch=d.beam_batch or d.n_beams, beam_chunk=beam_chunk)
         req.chunks_total = len(chunks)
         return int(foot)
 
@@ -245,22 +257,33 @@ class GpuExecutor:
 
     # -- synthesis --
     def synthesize(self, batch):
-        """Issue one batched synthesis for [(req, chunk)] on the synthesis stream."""
+        """Issue one batched synthesis for [(req, chunk)] on the synthesis
+        stream; chunks of requests marked for beam-chunked contraction are
+        issued one by one on the same stream."""
         torch, api = self.torch, self.api
-        items = []
+        items, single = [], []
         for req, c in batch:
             info = req.info
             self.synth_stream.wait_event(info["built_event"])
             p0 = sum(len(x) for x in info["chunks"][:c])
             out = info["out"][p0:p0 + len(info["chunks"][c])]
-            items.append((info["desc"], info["S"], info["plans"][c], out))
+            it = (info["desc"], info["S"], info["plans"][c], out)
+            (single if info.get("beam_chunk") else items).append((it, info.get("beam_chunk")))
             req.chunks_issued += 1
+        keep = []
         with torch.cuda.stream(self.synth_stream):
-            ws = torch.empty(max(api.prism_probe_batch_workspace(items), 1), dtype=torch.uint8, device="cuda")
-            api.prism_probe_outputs_batched(items, self.precision, ws=ws)
+            if items:
+                its = [it for it, _ in items]
+                ws = torch.empty(max(api.prism_probe_batch_workspace(its), 1), dtype=torch.uint8, device="cuda")
+                api.prism_probe_outputs_batched(its, self.precision, ws=ws)
+                keep.append(ws)
+            for (d, S, plan, out), bc in single:
+                ws = torch.empty(api.prism_probe_chunked_workspace(d, plan, bc), dtype=torch.uint8, device="cuda")
+                api.prism_probe_outputs_chunked(d, S, plan, self.precision, bc, ws=ws, out=out)
+                keep.append(ws)
             ev = torch.cuda.Event()
             ev.record(self.synth_stream)
-        self.inflight.append((ev, list(batch), ws))
+        self.inflight.append((ev, list(batch), keep))
 
     def finished_batches(self):
         """Batches whose synthesis completed (in issue order)."""
@@ -278,6 +301,15 @@ class GpuExecutor:
 
     def chunks_left(self, req: Request):
         return range(req.chunks_issued, req.chunks_total)
+
+
+def _chunked_ws(d, plan, beam_chunk):
+    import ctypes
+
+    from ._lib import check, lib
+    need = ctypes.c_size_t()
+    check(lib.prism_probe_chunked_workspace(ctypes.byref(d), ctypes.byref(plan), int(beam_chunk), ctypes.byref(need)))
+    return need.value
 
 
 # ---------------------------------------------------------------- the loop --

@@ -118,3 +118,20 @@ def test_probe_plan_sizes():
     with pytest.raises(P.PrismError) as e:
         P.prism_probe_plan_init(d, np.array([[np.nan, 0.0]]))
     assert e.value.code == P.PRISM_E_INVAL
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """The library and PyTorch share one HIP runtime even when the package is
+    imported before torch (two runtimes would make torch's streams and
+    memory invalid for the library)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1706_08563_amd\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "libs = {l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}\n"
+            "print(len(libs))\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"

@@ -31,7 +31,8 @@ def _requests():
 def _run(reqs, prec, **kw):
     import torch
     from paper_1706_08563_amd.serve import GpuExecutor, Scheduler, serve
-    ex = GpuExecutor(prec, probe_chunk_bytes=kw.pop("chunk", 1 << 30))
+    ex = GpuExecutor(prec, probe_chunk_bytes=kw.pop("chunk", 1 << 30),
+                     split_limit_bytes=kw.pop("split_limit", 8 << 30))
     sched = Scheduler(int(64e9), **kw)
     serve(reqs, ex, sched)
     torch.cuda.synchronize()
@@ -69,3 +70,19 @@ def test_served_request_matches_oracle():
     err = O.rel_err(r.result, ref)
     say(f"  rel_all = {err:.3e}")
     assert err <= 1e-4
+
+
+def test_beam_chunked_requests_in_the_mix():
+    """Requests whose split S-matrix exceeds the executor's limit are
+    contracted in beam chunks; their results agree with the batched path to
+    FP32 summation order and the others are unchanged."""
+    say("serving: beam-chunked contraction for requests above the split limit")
+    mixed = _requests()
+    _run(mixed, 1, max_building=4, max_jobs=8, split_limit=1 << 20)
+    assert all(r.info.get("beam_chunk") for r in mixed if r.n >= 256)
+    ref = _requests()
+    _run(ref, 1, max_building=4, max_jobs=8)
+    for a, b in zip(mixed, ref):
+        err = O.rel_err(a.result, b.result)
+        say(f"  request {a.rid} (n={a.n}, beam chunk {a.info.get('beam_chunk')}): rel diff {err:.3e}")
+        assert err <= 1e-5

@@ -112,6 +112,36 @@ def test_streaming_synthesis(P, n, L, f, a, prec, chunk):
     assert np.linalg.norm(got4 - ref4) / np.linalg.norm(ref4) <= TOL
 
 
+@pytest.mark.parametrize("prec,chunk", [(0, 37), (1, 16), (2, 100)])
+def test_chunked_synthesis_device_s(P, prec, chunk):
+    import torch
+    n, L, f, a = 256, 20.0, 2, 0.02
+    g = P.prism_grid_init((L, L, 2.0), 2.0, n)
+    d = P.prism_smatrix_plan(g, 200e3, a, f)
+    say(f"beam-chunked synthesis from device S: beams={d.n_beams} chunk={chunk} precision={prec}")
+    rng = np.random.default_rng(61 + prec)
+    S = W.random_complex((d.n_beams, d.ns, d.ns), rng)
+    xy = np.concatenate([W.random_positions((L, L), 7, rng), [[0.0, 0.0]]])
+    plan = P.prism_probe_plan_upload(d, xy, C1=8.0)
+    Sh = torch.from_numpy(S).pin_memory()
+    Sd = Sh.cuda()
+    D_chk = P.prism_probe_outputs_chunked(d, Sd, plan, prec, chunk)
+    D_str = P.prism_probe_outputs_streaming(d, Sh, plan, prec, chunk)
+    D_res = P.prism_probe_outputs(d, Sd, plan, prec)
+    I_chk = P.prism_probe_outputs_chunked(d, Sd, plan, prec, chunk, diffraction=True)
+    torch.cuda.synchronize()
+    a_, b_ = D_chk.cpu().numpy(), D_str.cpu().numpy()
+    assert np.array_equal(a_, b_)                       # same kernels, same chunks
+    assert O.rel_err(a_, D_res.cpu().numpy()) <= (1e-5 if prec < 2 else 1e-3)
+    beams = P.prism_beam_list(d).astype(np.int64)
+    if prec < 2:
+        ref = O.prism_outputs(S.astype(np.complex128), beams, L, n, d.lambda_, f, xy, C1=8.0)
+        assert O.rel_err(a_, ref) <= TOL
+        ref4 = O.prism_diffraction(S.astype(np.complex128), beams, L, n, d.lambda_, f, xy, C1=8.0)
+        got4 = I_chk.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(got4 - ref4) / np.linalg.norm(ref4) <= TOL
+
+
 def test_memory_plan_streaming_end_to_end(P):
     import torch
     from paper_1706_08563_amd import memory as M
