@@ -136,11 +136,14 @@ struct Fft {
     static constexpr int NST = Plan<L>::NST;
     static constexpr int LPT = L / E;                 // lanes per transform (<= 64)
     static_assert(LPT <= 64, "one transform must fit in a wavefront");
-    // Exchange buffers insert one pad slot every 2^PADSH elements: with 32
-    // four-byte banks serving 16 lanes of a 64-bit access per cycle, this
-    // spreads the strided stage writes and keeps the natural-order reads
-    // nearly conflict-free (one slot every 8 for L <= 64, every 16 above).
-    static constexpr int PADSH = L <= 64 ? 3 : 4;
+    // Exchange buffers insert one pad slot every 2^PADSH elements, which
+    // spreads the strided stage writes over the LDS banks: one slot every 8
+    // elements (measured best for the 512-point passes), or every 16 for the
+    // lengths L whose bit log2(L) is set in PRISM_PAD16_MASK.
+#ifndef PRISM_PAD16_MASK
+#define PRISM_PAD16_MASK 128      // L = 128 (the 128-pixel window transforms)
+#endif
+    static constexpr int PADSH = ((PRISM_PAD16_MASK) >> __builtin_ctz(L)) & 1 ? 4 : 3;
     static constexpr int LDS = L + (L >> PADSH);      // padded exchange buffer (float2)
 
     static constexpr int radix(int s) { return Plan<L>::R[s]; }

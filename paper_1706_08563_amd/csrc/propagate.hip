@@ -43,6 +43,9 @@ constexpr int WG = 256;      // 4 wavefronts
 #ifndef PRISM_PASSA_TPREF
 #define PRISM_PASSA_TPREF 1      // 1: transmission row requested before the inverse row transforms
 #endif
+#ifndef PRISM_PASSB_LDSDMA
+#define PRISM_PASSB_LDSDMA 0     // 1: next column prefetched by direct global->LDS loads
+#endif
 #ifndef PRISM_PASSB_COLS
 #define PRISM_PASSB_COLS 8       // adjacent columns per transform group in pass B (pipelined loads)
 #endif
@@ -288,43 +291,82 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
         return;
     } else {
         // software pipeline over NC columns: the next column's loads are in
-        // flight while this one is transformed
+        // flight while this one is transformed.  The propagator factors are
+        // read before the loop: vector memory waits complete in issue order,
+        // so a table load inside the loop would also wait for the prefetch.
+        float2 pk[E], pjs[NC];
+#pragma unroll
+        for (int i = 0; i < E; ++i) pk[i] = tb.prop[lt + LPT * i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pjs[c] = tb.prop[j0 + c];
+#if PRISM_PASSB_LDSDMA
+        // the next column lands straight in this wave's LDS slot (lane l of
+        // load i writes 16 bytes at float4 index 64 i + l), holding no VGPRs
+        __shared__ float4 pre[4 * 64 * E];
+        float4* const pw = pre + wave * 64 * E;
+        auto dma = [&](const float2* colp) {
+            const float4* c4 = reinterpret_cast<const float4*>(colp);
+#pragma unroll
+            for (int i = 0; i < E; ++i)
+                __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(c4 + lt + LPT * i),
+                                                 (void __attribute__((address_space(3)))*)(pw + 64 * i), 16, 0, 0);
+        };
+        dma(Wi + (size_t)j0 * wave_col_stride(N));
+#else
         float4 cur[E], nxt[E];
         {
             const float4* c4 = reinterpret_cast<const float4*>(Wi + (size_t)j0 * wave_col_stride(N));
 #pragma unroll
             for (int i = 0; i < E; ++i) cur[i] = c4[lt + LPT * i];
         }
+#endif
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int j = j0 + c;
             float2* col = Wi + (size_t)j * wave_col_stride(N);
             float4* col4 = reinterpret_cast<float4*>(col);
+#if PRISM_PASSB_LDSDMA
+            // this column's loads are the oldest outstanding vector memory
+            // operations; only the previous column's E stores may follow them
+            if (c == 0) __builtin_amdgcn_s_waitcnt(0x0F70);            // vmcnt(0)
+            else __builtin_amdgcn_s_waitcnt(0x0F70 | E);              // vmcnt(E)
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const float4 v = pw[64 * i + lane];
+                e[i] = make_float2(v.x, v.y);
+                o[i] = make_float2(v.z, v.w);
+            }
+            __builtin_amdgcn_s_waitcnt(0xC07F);                        // lgkmcnt(0): slot read before refill
+            wave_sync();
+            if (c + 1 < NC) dma(col + wave_col_stride(N));
+#else
             if (c + 1 < NC) {
                 const float4* n4 = reinterpret_cast<const float4*>(col + wave_col_stride(N));
 #pragma unroll
                 for (int i = 0; i < E; ++i) nxt[i] = n4[lt + LPT * i];
             }
-            const int kxj = j < N / 4 ? j : j - N / 2;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 e[i] = make_float2(cur[i].x, cur[i].y);
                 o[i] = make_float2(cur[i].z, cur[i].w);
             }
+#endif
+            const int kxj = j < N / 4 ? j : j - N / 2;
             if constexpr (PRISM_PASSB_ILP) {
                 F::template run2<-1>(e, o, lds, lds2, tw, lt);
             } else {
                 F::template run<-1>(e, lds, tw, lt);
                 F::template run<-1>(o, lds, tw, lt);
             }
-            const float2 pj = tb.prop[j];
+            const float2 pj = pjs[c];
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 int jp = lt + LPT * i;
                 int ky = jp < N / 4 ? jp : jp - N / 2;
                 float2 psi = cadd(e[i], cmul(btw[i], o[i]));
                 bool in = 16 * (kxj * kxj + ky * ky) < N * N;
-                e[i] = in ? cmul(psi, cmul(pj, tb.prop[jp])) : make_float2(0.f, 0.f);
+                e[i] = in ? cmul(psi, cmul(pj, pk[i])) : make_float2(0.f, 0.f);
             }
             if constexpr (MODE == PASSB_LAST_I) {
                 float* dst = inten + ((size_t)item * L + j) * L;
@@ -348,10 +390,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
 #pragma unroll
                 for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
             }
+#if !PRISM_PASSB_LDSDMA
             if (c + 1 < NC) {
 #pragma unroll
                 for (int i = 0; i < E; ++i) cur[i] = nxt[i];
             }
+#endif
         }
     }
 }
