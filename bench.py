@@ -86,7 +86,8 @@ def parse():
     ap.add_argument("--cpu-probes", type=int, default=12)
     ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson stream of mixed requests)")
     ap.add_argument("--requests", type=int, default=40)
-    ap.add_argument("--load", type=float, default=0.8, help="offered load against the modelled capacity")
+    ap.add_argument("--loads", default="0.4,0.8,1.6",
+                    help="offered loads, as fractions of the capacity measured by a saturation run")
     ap.add_argument("--grids", default="256,512,1024,2048")
     ap.add_argument("--precision-study", action="store_true", help="2048^2 f=8 contraction precision study")
     ap.add_argument("--pmc-driver", action="store_true",
@@ -148,35 +149,37 @@ def run_serving(args):
 
     prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
     grids = tuple(int(x) for x in args.grids.split(","))
-    params = W.serving_stream(args.requests, 1.0, grids=grids)
-    # offered load: rate = load / modelled mean service time, the model being
-    # the 1024^2 build cost per beam-slice scaled by n^2 log n, plus synthesis
-    per_bs = 4.6e-6
-    cost = []
-    for p in params:
-        r = SV.Request(**p)
-        g = P.prism_grid_init(r.cell, 2.0, r.n)
-        d = P.prism_smatrix_plan(g, r.E0, r.alpha_max, r.f)
-        scale = (r.n / 1024.0) ** 2 * math.log2(r.n) / 10.0
-        cost.append(per_bs * d.n_beams * r.n_slices * scale + 1.5e-6 * r.n_probes * d.n_beams / 1245.0)
-    rate = args.load / float(np.mean(cost))
-    params = W.serving_stream(args.requests, rate, grids=grids)
-    reqs = []
-    for p in params:
-        r = SV.Request(**p)
-        r.sample = W.serving_sample(r.cell, r.seed)
-        reqs.append(r)
+    loads = [float(x) for x in args.loads.split(",")]
     free, total = torch.cuda.mem_get_info()
     cap = int(0.8 * free)
-    log(f"serving {len(reqs)} requests at {rate:.3f}/s, budget {cap / 1e9:.1f} GB")
-    ex = SV.GpuExecutor(prec)
-    sched = SV.Scheduler(cap, max_building=4, max_jobs=24)
-    t0 = time.perf_counter()
-    SV.serve(reqs, ex, sched, on_done=lambda r: log(f"  done {r.rid} n={r.n} f={r.f} S={r.n_slices} "
-                                                    f"P={r.n_probes} latency {r.latency:.2f} s"))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    summ = SV.summarize(sched, wall)
+
+    def run(rate, tag):
+        """The request stream (same requests, arrivals scaled to `rate`)
+        through a fresh scheduler and executor; returns (scheduler, wall s)."""
+        reqs = []
+        for p in W.serving_stream(args.requests, rate, grids=grids):
+            r = SV.Request(**p)
+            r.sample = W.serving_sample(r.cell, r.seed)
+            reqs.append(r)
+        log(f"[{tag}] serving {len(reqs)} requests at {rate:.3f}/s, budget {cap / 1e9:.1f} GB")
+        ex = SV.GpuExecutor(prec, jobs_per_request=4)
+        sched = SV.Scheduler(cap, max_building=4, max_jobs=24, jobs_per_request=4)
+        t0 = time.perf_counter()
+        SV.serve(reqs, ex, sched, on_done=lambda r: log(f"  [{tag}] done {r.rid} n={r.n} f={r.f} S={r.n_slices} "
+                                                        f"P={r.n_probes} latency {r.latency:.2f} s"))
+        torch.cuda.synchronize()
+        return sched, time.perf_counter() - t0
+
+    # standalone capacity: every request present at t = 0 (saturation)
+    sat, sat_wall = run(0.0, "saturation")
+    capacity = len(sat.done) / sat_wall
+    sweep = {}
+    for ld in loads:
+        sc, wl = run(ld * capacity, f"load {ld}")
+        sweep[ld] = (sc, wl, SV.summarize(sc, wl))
+    ld0 = 0.8 if 0.8 in sweep else loads[0]
+    sched, wall, summ = sweep[ld0]
+    rate = ld0 * capacity
     # alone vs in the mix, for the three smallest requests
     small = sorted(sched.done, key=lambda r: r.n * r.n * r.n_slices)[:3]
     diffs = []
@@ -208,9 +211,15 @@ def run_serving(args):
            "value": summ["probes_per_s"], "unit": "probe positions/s", "n_gpus": 1,
            "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
            "requests": summ["requests"], "rejected": summ["rejected"], "probes": summ["probes"],
-           "wall_s": wall, "arrival_rate_per_s": rate, "offered_load": args.load,
+           "wall_s": wall, "arrival_rate_per_s": rate, "offered_load": ld0,
+           "capacity_requests_per_s": capacity, "saturation_probes_per_s": SV.summarize(sat, sat_wall)["probes_per_s"],
+           "load_sweep": {str(k): {"probes_per_s": v[2]["probes_per_s"], "p50_latency_s": v[2]["p50_latency_s"],
+                                   "p99_latency_s": v[2]["p99_latency_s"], "wall_s": v[1]}
+                          for k, v in sweep.items()},
            "hbm_budget_GB": cap / 1e9, "peak_reserved_GB": summ["peak_hbm_reserved"] / 1e9,
            "precision": args.precision, "grids": list(grids),
+           "beam_chunked_requests": sum(1 for r in sched.done if r.info.get("beam_chunk")),
+           "largest_request_beams": max((r.info.get("n_beams", 0) for r in sched.done), default=0),
            "alone_vs_mix_max_abs_diff": max(diffs) if diffs else None,
            "sequential_multislice_s_extrapolated": ms_time,
            "speedup_vs_sequential_multislice": ms_time / wall if wall > 0 else None,

@@ -77,12 +77,16 @@ class Request:
 class Scheduler:
     """Admission, bookkeeping and batch formation; no device state."""
 
-    def __init__(self, capacity: int, max_building: int = 4, max_jobs: int = 24, aging: int = 8):
+    def __init__(self, capacity: int, max_building: int = 4, max_jobs: int = 24, aging: int = 8,
+                 jobs_per_request: int = 4):
         self.capacity = int(capacity)
         self.used = 0
         self.max_building = max_building
         self.max_jobs = max_jobs
         self.aging = aging
+        # probe chunks of one request per batch (bounds a request's share of
+        # the batch workspace, which its footprint accounts for)
+        self.jobs_per_request = jobs_per_request
         self.queue: list[Request] = []
         self.building: list[Request] = []
         self.built: list[Request] = []
@@ -150,12 +154,15 @@ class Scheduler:
 
     def next_batch(self, chunks_left) -> list:
         """Up to max_jobs (request, chunk index) pairs from built requests,
-        oldest request first.  `chunks_left(req)` gives the chunks not yet issued."""
+        oldest request first, at most jobs_per_request per request.
+        `chunks_left(req)` gives the chunks not yet issued."""
         batch = []
         for req in sorted(self.built, key=lambda r: r.arrival):
-            for c in chunks_left(req):
+            for k, c in enumerate(chunks_left(req)):
                 if len(batch) >= self.max_jobs:
                     return batch
+                if k >= self.jobs_per_request:
+                    break
                 batch.append((req, c))
         return batch
 
@@ -180,7 +187,7 @@ class GpuExecutor:
     """Runs requests with libprism on the current HIP device."""
 
     def __init__(self, precision: int, probe_chunk_bytes: int = 1 << 30, build_ws_bytes: int = 16 << 30,
-                 split_limit_bytes: int = 8 << 30):
+                 split_limit_bytes: int = 8 << 30, jobs_per_request: int = 4):
         import torch
 
         from . import api
@@ -193,6 +200,7 @@ class GpuExecutor:
         # S-matrices whose split copy would exceed this are contracted in beam
         # chunks (prism_probe_outputs_chunked) instead of in the shared batch
         self.split_limit_bytes = split_limit_bytes
+        self.jobs_per_request = jobs_per_request      # must match the scheduler's
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
 
@@ -220,10 +228,14 @@ class GpuExecutor:
         split_bytes = d.ns * d.ns * kb * 128
         beam_chunk = 0
         if split_bytes > self.split_limit_bytes:
+            # beam-chunked chunks run one after another on one shared workspace
             beam_chunk = max(16, (self.split_limit_bytes // (d.ns * d.ns * 128)) * 16)
             ws = max(_chunked_ws(d, p, beam_chunk) for p in plans)
         else:
-            ws = max(p.ws_bytes for p in plans)
+            # a batch holds up to jobs_per_request chunks of this request, each
+            # with its own coefficients and windows, plus one split S
+            per_chunk = max(p.ws_bytes for p in plans) - split_bytes
+            ws = split_bytes + min(self.jobs_per_request, len(plans)) * per_chunk
         foot = (g.n_slices * g.n * g.n * 4 + d.smatrix_bytes + d.build_ws_bytes
                 + sum(p.plan_bytes for p in plans) + ws + len(xy) * n_bins * 4)
         req.info.update(grid=g, desc=d, chunks=chunks, n_bins=n_bins, n_beams=d.n_beams, m_win=d.m_win,
@@ -277,9 +289,12 @@ class GpuExecutor:
                 ws = torch.empty(max(api.prism_probe_batch_workspace(its), 1), dtype=torch.uint8, device="cuda")
                 api.prism_probe_outputs_batched(its, self.precision, ws=ws)
                 keep.append(ws)
-            for (d, S, plan, out), bc in single:
-                ws = torch.empty(api.prism_probe_chunked_workspace(d, plan, bc), dtype=torch.uint8, device="cuda")
-                api.prism_probe_outputs_chunked(d, S, plan, self.precision, bc, ws=ws, out=out)
+            if single:
+                # one workspace serves every beam-chunked item (same stream, in order)
+                need = max(api.prism_probe_chunked_workspace(d, plan, bc) for (d, S, plan, out), bc in single)
+                ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+                for (d, S, plan, out), bc in single:
+                    api.prism_probe_outputs_chunked(d, S, plan, self.precision, bc, ws=ws, out=out)
                 keep.append(ws)
             ev = torch.cuda.Event()
             ev.record(self.synth_stream)

@@ -141,3 +141,14 @@ def test_out_of_order_completion():
     sched, _ = _run(reqs, capacity=100)
     assert reqs[1].t_done < reqs[0].t_done
     assert [r.rid for r in sched.done] == [1, 0]
+
+
+def test_batches_take_at_most_jobs_per_request_chunks_of_one_request():
+    reqs = [_req(0, 0.0, foot=10, chunks=11), _req(1, 0.0, foot=10, chunks=2)]
+    sched, ex = _run(reqs, capacity=100, max_building=2, max_jobs=24, jobs_per_request=3)
+    for b in ex.batches:
+        for rid in {r for r, _ in b}:
+            assert sum(1 for r, _ in b if r == rid) <= 3
+    issued = sorted(x for b in ex.batches for x in b)
+    assert issued == sorted([(0, c) for c in range(11)] + [(1, c) for c in range(2)])
+    assert len(sched.done) == 2

@@ -186,7 +186,10 @@ def serving_stream(n_requests: int, rate: float, seed: int = 4, grids=(256, 512,
     nanoparticle-in-amorphous recipe seeded with 1000 + i.
     """
     rng = np.random.default_rng(seed)
-    t = np.cumsum(rng.exponential(1.0 / rate, size=n_requests)) if rate > 0 else np.zeros(n_requests)
+    # unit-rate gaps drawn first in every case, so the requests themselves do
+    # not depend on the rate (rate 0: everything arrives at t = 0)
+    gaps = rng.exponential(1.0, size=n_requests)
+    t = np.cumsum(gaps) / rate if rate > 0 else np.zeros(n_requests)
     out = []
     for i in range(n_requests):
         s = int(rng.integers(scan[0], scan[1] + 1))
