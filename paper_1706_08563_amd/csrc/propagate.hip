@@ -41,10 +41,14 @@ constexpr int WG = 256;      // 4 wavefronts
 #define PRISM_PASSB_WPE 1
 #endif
 #ifndef PRISM_PASSA_TPREF
-#define PRISM_PASSA_TPREF 1      // 1: transmission row requested before the inverse row transforms
+#define PRISM_PASSA_TPREF 4096   // largest n whose transmission row is requested before the inverse
+                                 // row transforms (measured better at n = 1024 and 2048)
 #endif
 #ifndef PRISM_PASSB_LDSDMA
 #define PRISM_PASSB_LDSDMA 0     // 1: next column prefetched by direct global->LDS loads
+#endif
+#ifndef PRISM_PASSB_DEPTH
+#define PRISM_PASSB_DEPTH 1      // columns prefetched ahead in registers (1 or 2)
 #endif
 #ifndef PRISM_PASSB_COLS
 #define PRISM_PASSB_COLS 8       // adjacent columns per transform group in pass B (pipelined loads)
@@ -146,7 +150,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
         // so the load latency hides behind them
         float4 trow[E];
         const float4* Trow = reinterpret_cast<const float4*>(T + (size_t)y * N);
-        if constexpr (PRISM_PASSA_TPREF) {
+        if constexpr (N <= PRISM_PASSA_TPREF) {
 #pragma unroll
             for (int i = 0; i < E; ++i) trow[i] = Trow[lt + LPT * i];
         }
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
                 F::template run<+1>(o, row, tw, lt);
             }
         }
-        if constexpr (!PRISM_PASSA_TPREF) {
+        if constexpr (N > PRISM_PASSA_TPREF) {
 #pragma unroll
             for (int i = 0; i < E; ++i) trow[i] = Trow[lt + LPT * i];
         }
@@ -313,11 +317,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
         };
         dma(Wi + (size_t)j0 * wave_col_stride(N));
 #else
-        float4 cur[E], nxt[E];
-        {
-            const float4* c4 = reinterpret_cast<const float4*>(Wi + (size_t)j0 * wave_col_stride(N));
+        // ring of DEPTH + 1 column buffers: slot c % (DEPTH + 1) holds column c
+        constexpr int DEPTH = PRISM_PASSB_DEPTH;
+        float4 ring[DEPTH + 1][E];
 #pragma unroll
-            for (int i = 0; i < E; ++i) cur[i] = c4[lt + LPT * i];
+        for (int d = 0; d < DEPTH && d < NC; ++d) {
+            const float4* c4 = reinterpret_cast<const float4*>(Wi + (size_t)(j0 + d) * wave_col_stride(N));
+#pragma unroll
+            for (int i = 0; i < E; ++i) ring[d][i] = c4[lt + LPT * i];
         }
 #endif
 #pragma unroll
@@ -341,15 +348,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
             wave_sync();
             if (c + 1 < NC) dma(col + wave_col_stride(N));
 #else
-            if (c + 1 < NC) {
-                const float4* n4 = reinterpret_cast<const float4*>(col + wave_col_stride(N));
+            if (c + DEPTH < NC) {
+                const float4* n4 = reinterpret_cast<const float4*>(col + DEPTH * wave_col_stride(N));
 #pragma unroll
-                for (int i = 0; i < E; ++i) nxt[i] = n4[lt + LPT * i];
+                for (int i = 0; i < E; ++i) ring[(c + DEPTH) % (DEPTH + 1)][i] = n4[lt + LPT * i];
             }
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                e[i] = make_float2(cur[i].x, cur[i].y);
-                o[i] = make_float2(cur[i].z, cur[i].w);
+                e[i] = make_float2(ring[c % (DEPTH + 1)][i].x, ring[c % (DEPTH + 1)][i].y);
+                o[i] = make_float2(ring[c % (DEPTH + 1)][i].z, ring[c % (DEPTH + 1)][i].w);
             }
 #endif
             const int kxj = j < N / 4 ? j : j - N / 2;
@@ -390,13 +397,94 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
 #pragma unroll
                 for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
             }
-#if !PRISM_PASSB_LDSDMA
-            if (c + 1 < NC) {
-#pragma unroll
-                for (int i = 0; i < E; ++i) cur[i] = nxt[i];
-            }
-#endif
         }
+    }
+}
+
+// Tile-staged column pass for interior slices (one transform per wavefront,
+// n >= 1024): a workgroup stages TC whole columns into LDS with all its loads
+// in flight at once (as pass A stages its row tile), then each wavefront
+// transforms its columns from LDS, using each column's own LDS slots as the
+// two padded exchange buffers of its even and odd transforms, and writes the
+// result straight from registers.
+#ifndef PRISM_PASSB_TILE_MIN
+#define PRISM_PASSB_TILE_MIN 2048   // smallest n whose interior column passes use k_pass_b_tile
+#endif
+template <int N>
+struct PassBTile {
+    using F = Fft<N / 2>;
+    // measured: 2.08 -> 2.23 ms at n = 1024 (slower), 24.6 -> 16.4 ms at n = 2048
+    static constexpr bool ok = F::LPT == 64 && N >= PRISM_PASSB_TILE_MIN;   // one transform per wavefront
+    static constexpr int TC = N <= 1024 ? 8 : 4;               // columns per workgroup
+    static constexpr int CS = 2 * F::LDS;                     // LDS slots per column (e and o buffers)
+};
+
+template <int N>
+__global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, PropTables tb, int n_items) {
+    using T = PassBTile<N>;
+    using F = typename T::F;
+    constexpr int L = N / 2, E = F::E, LPT = F::LPT, TC = T::TC, CS = T::CS;
+    static_assert(LPT == 64, "one transform per wavefront");
+    __shared__ float2 tile[TC * CS];
+    const int item = blockIdx.x % n_items;
+    const int jb = (blockIdx.x / n_items) * TC;
+    const int tid = threadIdx.x, wave = tid >> 6, lt = tid & 63;
+    float2* const Wi = W + (size_t)item * L * wave_col_stride(N);
+    {
+        // column c, float4 m = rows (2m, 2m+1): even sample to buffer 0, odd to buffer 1
+        constexpr int NLD = TC * L / WG;
+        static_assert((TC * L) % WG == 0, "tile must split evenly over the workgroup");
+        float4 ld[NLD];
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, c = idx / L, m = idx % L;
+            ld[k] = reinterpret_cast<const float4*>(Wi + (size_t)(jb + c) * wave_col_stride(N))[m];
+        }
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int idx = tid + k * WG, c = idx / L, m = idx % L;
+            tile[c * CS + F::pad(m)] = make_float2(ld[k].x, ld[k].y);
+            tile[c * CS + F::LDS + F::pad(m)] = make_float2(ld[k].z, ld[k].w);
+        }
+    }
+    typename F::Twiddles tw;
+    tw.load(tb.tw_half, lt);
+    float2 btw[E], pk[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        btw[i] = tb.band_tw[lt + LPT * i];
+        pk[i] = tb.prop[lt + LPT * i];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int c = wave; c < TC; c += 4) {
+        const int j = jb + c;
+        float2* const xe = tile + c * CS;
+        float2* const xo = xe + F::LDS;
+        float2 e[E], o[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            e[i] = xe[F::pad(lt + LPT * i)];
+            o[i] = xo[F::pad(lt + LPT * i)];
+        }
+        F::template run<-1>(e, xe, tw, lt);
+        F::template run<-1>(o, xo, tw, lt);
+        const int kxj = j < N / 4 ? j : j - N / 2;
+        const float2 pj = tb.prop[j];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int jp = lt + LPT * i;
+            const int ky = jp < N / 4 ? jp : jp - N / 2;
+            const float2 psi = cadd(e[i], cmul(btw[i], o[i]));
+            const bool in = 16 * (kxj * kxj + ky * ky) < N * N;
+            e[i] = in ? cmul(psi, cmul(pj, pk[i])) : make_float2(0.f, 0.f);
+            o[i] = cmulc(e[i], btw[i]);
+        }
+        F::template run<+1>(e, xe, tw, lt);
+        F::template run<+1>(o, xo, tw, lt);
+        float4* col4 = reinterpret_cast<float4*>(Wi + (size_t)j * wave_col_stride(N));
+#pragma unroll
+        for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
     }
 }
 
@@ -404,6 +492,13 @@ template <int N, int MODE>
 static hipError_t pass_b_nm(float2* W, const PropTables& tb, const float2* aux, float* inten, const int* ky_max,
                             const double2* xy, double inv_L, float amp, int n_items, hipStream_t st) {
     constexpr int L = N / 2, LPT = Fft<L>::LPT, CPB = 4 * (64 / LPT) * PassBCols<N, MODE>::value;
+    if constexpr (MODE == PASSB_MID && PassBTile<N>::ok) {
+        constexpr int TC = PassBTile<N>::TC;
+        static_assert(L % TC == 0, "columns must split into whole tiles");
+        dim3 grid((unsigned)((size_t)n_items * (L / TC)));
+        hipLaunchKernelGGL((k_pass_b_tile<N>), grid, dim3(WG), 0, st, W, tb, n_items);
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)((size_t)n_items * ((L + CPB - 1) / CPB)));
     hipLaunchKernelGGL((k_pass_b<N, MODE>), grid, dim3(WG), 0, st, W, tb, aux, inten, ky_max, xy, inv_L, amp,
                        n_items);
