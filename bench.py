@@ -90,6 +90,10 @@ def parse():
                     help="offered loads, as fractions of the capacity measured by a saturation run")
     ap.add_argument("--grids", default="256,512,1024,2048")
     ap.add_argument("--precision-study", action="store_true", help="2048^2 f=8 contraction precision study")
+    ap.add_argument("--streaming-study", action="store_true",
+                    help="single-transfer vs streaming memory model on the default workload: time and peak HBM")
+    ap.add_argument("--budget-fraction", type=float, default=0.1,
+                    help="streaming study: device budget as a fraction of the single-transfer footprint")
     ap.add_argument("--pmc-driver", action="store_true",
                     help="short program for hardware-counter runs: the default workload's build cut to 4 slices, "
                          "one synthesis of its probes, and a 256 MiB device copy for counter calibration")
@@ -316,6 +320,62 @@ def precision_study(args):
     print(json.dumps({"precision_study": res}), flush=True)
 
 
+def streaming_study(args):
+    """The paper's single-transfer vs streaming comparison ("Data
+    Streaming/Single-Transfer Benchmark") on the default workload: the whole
+    simulation (S-matrix build and synthesis of every probe) with the
+    potential and S-matrix resident, then with both in page-locked host memory
+    under a device budget of `budget_fraction` of the single-transfer
+    footprint; wall time and peak device memory of each, and the difference
+    of their outputs."""
+    import numpy as np
+    import torch
+
+    import paper_1706_08563_amd as P
+    from paper_1706_08563_amd import memory as MM
+    import workloads as W
+
+    prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
+    w = W.CONFIGS[args.config]
+    pos, sp = W.atoms_for(w)
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    V = P.prism_project_potential(pos, sp, w.species, g)
+    Vh = V.cpu().pin_memory()
+    xy = W.scan_positions(w.cell, *w.scan)
+    single = MM.plan_memory(g, w.E0, w.alpha_max, w.f, xy, 1 << 60)
+    budget = int(args.budget_fraction * single.single_bytes)
+    mp = MM.plan_memory(g, w.E0, w.alpha_max, w.f, xy, budget)
+    log(f"streaming study: single transfer {single.single_bytes / 1e9:.2f} GB; budget {budget / 1e9:.2f} GB -> "
+        f"{mp.mode}, beam batch {mp.desc.beam_batch}, beam chunk {mp.beam_chunk}, probe chunk {mp.probe_chunk}")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0, torch.cuda.max_memory_allocated() - base
+
+    MM.run_prism(single, V, xy, prec)            # warm-up (code objects, allocator)
+    d_single, t_single, m_single = timed(lambda: MM.run_prism(single, V, xy, prec))
+    del V
+    torch.cuda.empty_cache()
+    d_stream, t_stream, m_stream = timed(lambda: MM.run_prism(mp, Vh, xy, prec))
+    a, b = d_single.cpu().numpy().astype(np.float64), d_stream.cpu().numpy().astype(np.float64)
+    res = {"streaming_study": {
+        "workload": w.name, "precision": args.precision, "probes": len(xy), "beams": single.desc.n_beams,
+        "single_transfer": {"seconds": t_single, "peak_device_GB": m_single / 1e9,
+                            "planned_GB": single.single_bytes / 1e9},
+        "streaming": {"seconds": t_stream, "peak_device_GB": m_stream / 1e9, "planned_GB": mp.peak_bytes / 1e9,
+                      "budget_GB": budget / 1e9, "beam_batch": mp.desc.beam_batch, "beam_chunk": mp.beam_chunk,
+                      "probe_chunk": mp.probe_chunk},
+        "time_ratio_streaming_over_single": t_stream / t_single,
+        "peak_memory_ratio_single_over_streaming": m_single / max(m_stream, 1),
+        "rel_diff_outputs": float(np.linalg.norm(a - b) / np.linalg.norm(a))}}
+    print(json.dumps(res), flush=True)
+
+
 def pmc_driver(args):
     """One launch of every kernel of the default workload at its real per-launch
     size (the build cut to 4 slices: one first-slice and three interior launches
@@ -359,6 +419,9 @@ def main():
         return
     if args.pmc_driver:
         pmc_driver(args)
+        return
+    if args.streaming_study:
+        streaming_study(args)
         return
 
     import numpy as np

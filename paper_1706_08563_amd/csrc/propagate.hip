@@ -111,21 +111,26 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
     float2* Wi = W + (size_t)item * L * CS;
     const int tid = threadIdx.x;
 
+    // Tile element (yy, j): thread tid owns yy = tid % TR and j = tid / TR + JS k.
+    // JS is a multiple of the exchange padding period, so the padded LDS slot
+    // of j advances by a compile-time step: pad(j0 + JS k) = pad(j0) + JSP k.
+    static_assert((L * TR) % WG == 0, "tile must split evenly over the workgroup");
+    constexpr int NLD = L * TR / WG, JS = WG / TR, JSP = JS + (JS >> F::PADSH);
+    constexpr bool AFFINE = JS % (1 << F::PADSH) == 0;
+    const int yy0 = tid % TR, j0 = tid / TR;
+    float2* const gW = Wi + (size_t)j0 * CS + y0 + yy0;
+    float2* const sW = tile + yy0 * ROW + F::pad(j0);
+    auto lds_slot = [&](int k) -> float2& {
+        if constexpr (AFFINE) return sW[k * JSP];
+        else return tile[yy0 * ROW + F::pad(j0 + JS * k)];
+    };
     if constexpr (!FIRST) {
         // all loads of the tile in flight before the first LDS store
-        static_assert((L * TR) % WG == 0, "tile must split evenly over the workgroup");
-        constexpr int NLD = L * TR / WG;
         float2 ld[NLD];
 #pragma unroll
-        for (int k = 0; k < NLD; ++k) {
-            const int idx = tid + k * WG, yy = idx % TR, j = idx / TR;
-            ld[k] = Wi[(size_t)j * CS + y0 + yy];
-        }
+        for (int k = 0; k < NLD; ++k) ld[k] = gW[(size_t)k * JS * CS];
 #pragma unroll
-        for (int k = 0; k < NLD; ++k) {
-            const int idx = tid + k * WG, yy = idx % TR, j = idx / TR;
-            tile[yy * ROW + F::pad(j)] = ld[k];
-        }
+        for (int k = 0; k < NLD; ++k) lds_slot(k) = ld[k];
         __syncthreads();
     }
 
@@ -200,10 +205,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < L * TR / WG; ++k) {
-        const int idx = tid + k * WG, yy = idx % TR, j = idx / TR;
-        Wi[(size_t)j * CS + y0 + yy] = tile[yy * ROW + F::pad(j)];
-    }
+    for (int k = 0; k < NLD; ++k) gW[(size_t)k * JS * CS] = lds_slot(k);
 }
 
 template <int N>
