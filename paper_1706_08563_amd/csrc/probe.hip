@@ -186,11 +186,18 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
 // 16 beams (see kernels.hpp): S per (pixel tile, K step), C per (probe, K
 // step).  A workgroup (one 16 x 16 pixel tile x 64 probes) then copies each K
 // step's records straight into LDS and feeds the MFMAs; the next K step's
-// global loads are in flight while the current step's MFMAs run.  Wave w owns
-// tile rows 4w..4w+3 (four 16-pixel MFMA column blocks) and all four 16-probe
-// row blocks.
+// global loads are in flight while the current step's MFMAs run.  With W
+// wavefronts (4 or 8), wave w owns tile rows (16/W)w .. (16/W)(w+1)-1 (16-pixel
+// MFMA column blocks) and all W 16-probe row blocks: 16 W probes per workgroup.
+#ifndef PRISM_CONTRACT_WAVES
+#define PRISM_CONTRACT_WAVES 4   // wavefronts per contraction workgroup (4: 64 probes, 8: 128 probes)
+#endif
 namespace mfmac {
-constexpr int PC = 64;   // probes per workgroup
+constexpr int WAVES = PRISM_CONTRACT_WAVES;
+constexpr int NT = 64 * WAVES;        // threads per workgroup
+constexpr int PB = 16 / WAVES;        // tile rows (16-pixel MFMA column blocks) per wave
+constexpr int QB = 16 / PB;           // 16-probe row blocks
+constexpr int PC = 16 * QB;           // probes per workgroup
 }
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -323,10 +330,11 @@ hipError_t launch_coefficients_split(int precision, void* Csplit, const double2*
 }
 
 template <int NP>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_contract_mfma(ContractBatch batch) {
+__global__ __launch_bounds__(mfmac::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_contract_mfma(ContractBatch batch) {
     using namespace mfmac;
     constexpr int NCH = NP * 4;                 // 16-byte chunks per record
-    constexpr int CPT = PC * NCH / WG;          // C chunks staged per thread
+    constexpr int CPT = PC * NCH / NT;          // C chunks staged per thread
+    constexpr int SPT = 256 * NCH / NT;         // S chunks staged per thread
     __shared__ u32x4 Ss[256 * NCH];             // one K step of the tile (records as stored)
     __shared__ u32x4 Cl[PC * NCH];              // one K step of the probe chunk (records permuted)
     __shared__ int pidx[PC];
@@ -347,11 +355,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid < PC) pidx[tid] = tid < np ? tile_probes[pc0 + tid] : -1;
 
-    f32x4 accr[4][4], acci[4][4];
+    f32x4 accr[QB][PB], acci[QB][PB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < QB; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < PB; ++b) {
             accr[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
             acci[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
@@ -364,9 +372,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int ckey = rec_key<NP>(crow);
     const u32x4 zero = u32x4{0u, 0u, 0u, 0u};
 
-    u32x4 sreg[NCH], creg[CPT];
+    u32x4 sreg[SPT], creg[CPT];
 #pragma unroll
-    for (int j = 0; j < NCH; ++j) sreg[j] = Sg[j * 256];
+    for (int j = 0; j < SPT; ++j) sreg[j] = Sg[j * NT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) creg[j] = cq >= 0 ? Cg[j] : zero;
 
@@ -374,27 +382,27 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
     for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int j = 0; j < NCH; ++j) Ss[tid + j * 256] = sreg[j];
+        for (int j = 0; j < SPT; ++j) Ss[tid + j * NT] = sreg[j];
 #pragma unroll
         for (int j = 0; j < CPT; ++j) Cl[crow * NCH + ((cc0 + j) ^ ckey)] = creg[j];
         __syncthreads();
         if (k + 1 < K) {
 #pragma unroll
-            for (int j = 0; j < NCH; ++j) sreg[j] = Sg[(size_t)(k + 1) * 256 * NCH + j * 256];
+            for (int j = 0; j < SPT; ++j) sreg[j] = Sg[(size_t)(k + 1) * 256 * NCH + j * NT];
 #pragma unroll
             for (int j = 0; j < CPT; ++j) creg[j] = cq >= 0 ? Cg[(size_t)(k + 1) * NCH + j] : zero;
         }
         // B operand of lane group g: chunk part*4 + g (re beams 0-7, 8-15, im beams 0-7, 8-15)
-        u32x4 Bop[NP][4];
+        u32x4 Bop[NP][PB];
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb) {
-            const int pix = (4 * wave + pb) * TILE + col;
+        for (int pb = 0; pb < PB; ++pb) {
+            const int pix = (PB * wave + pb) * TILE + col;
             const int key = rec_key<NP>(pix);
 #pragma unroll
             for (int part = 0; part < NP; ++part) Bop[part][pb] = Ss[pix * NCH + ((part * 4 + g) ^ key)];
         }
 #pragma unroll
-        for (int qb = 0; qb < 4; ++qb) {
+        for (int qb = 0; qb < QB; ++qb) {
             const int row = 16 * qb + col;
             const int key = rec_key<NP>(row);
             // A_r = [Cr | -Ci]: chunk part*4 + g, negated for g >= 2; A_i = [Ci | Cr]: chunk part*4 + (g ^ 2)
@@ -406,7 +414,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 Ai[part] = Cl[row * NCH + ((part * 4 + (g ^ 2)) ^ key)];
             }
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb) {
+            for (int pb = 0; pb < PB; ++pb) {
                 accr[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ar[0]), as_bf16x8(Bop[0][pb]),
                                                                       accr[qb][pb], 0, 0, 0);
                 acci[qb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(Ai[0]), as_bf16x8(Bop[0][pb]),
@@ -427,15 +435,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     // ---- epilogue: D row = probe 16 qb + 4 g + r, column = pixel
 #pragma unroll
-    for (int qb = 0; qb < 4; ++qb)
+    for (int qb = 0; qb < QB; ++qb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = pidx[16 * qb + 4 * g + r];
             if (q < 0) continue;
             const int2 c0 = corner[q];
 #pragma unroll
-            for (int pb = 0; pb < 4; ++pb) {
-                const int py = ty0 + 4 * wave + pb, px = tx0 + col;
+            for (int pb = 0; pb < PB; ++pb) {
+                const int py = ty0 + PB * wave + pb, px = tx0 + col;
                 const int v = (py - c0.y) & (ns - 1);
                 const int u = (px - c0.x) & (ns - 1);
                 if (v < m && u < m) {
@@ -480,9 +488,9 @@ hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_
         if (precision == 0)
             hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, b);
         else if (precision == 1)
-            hipLaunchKernelGGL(k_contract_mfma<2>, grid, dim3(WG), 0, st, b);
+            hipLaunchKernelGGL(k_contract_mfma<2>, grid, dim3(mfmac::NT), 0, st, b);
         else
-            hipLaunchKernelGGL(k_contract_mfma<1>, grid, dim3(WG), 0, st, b);
+            hipLaunchKernelGGL(k_contract_mfma<1>, grid, dim3(mfmac::NT), 0, st, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
