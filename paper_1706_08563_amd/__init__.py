@@ -18,6 +18,6 @@ from .api import (  # noqa: F401
     prism_probe_batch_workspace, prism_probe_outputs_batched, prism_probe_diffraction,
     prism_streaming_build_workspace, prism_build_smatrix_streaming, prism_probe_streaming_workspace,
     prism_probe_outputs_streaming, multislice_streaming_workspace, multislice_outputs_streaming,
-    prism_probe_chunked_workspace, prism_probe_outputs_chunked,
+    prism_probe_chunked_workspace, prism_probe_outputs_chunked, prism_set_build_streams,
 )
 from . import _lib  # noqa: F401

@@ -335,6 +335,12 @@ def multislice_outputs_streaming(grid: prism_grid, E0: float, alpha_max: float, 
     return out
 
 
+def prism_set_build_streams(n: int):
+    """1: the S-matrix build runs on the current stream only; 2 (default): two
+    halves of each beam batch overlap on the current and a partner stream."""
+    check(lib.prism_set_build_streams(int(n)))
+
+
 # ---------------------------------------------------------------- timing --
 def prism_timing_enable(enable: bool = True):
     check(lib.prism_timing_enable(1 if enable else 0))

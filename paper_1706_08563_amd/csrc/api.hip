@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -509,6 +512,46 @@ int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap) {
     return PRISM_OK;
 }
 
+// ------------------------------------------------ overlapped build streams --
+// The S-matrix build runs the two halves of each beam batch on the caller's
+// stream and on a partner stream (one per caller stream, default priority,
+// kept for the life of the process), the partner starting one pass later, so
+// that row passes (bound by VALU issue) of one half share the GPU with column
+// passes (bound by memory latency) of the other, each kernel at its own
+// occupancy.
+std::atomic<int> g_build_streams{2};
+std::mutex g_partner_mu;
+std::map<hipStream_t, hipStream_t> g_partner;
+
+int partner_stream(hipStream_t st, hipStream_t* out) {
+    std::lock_guard<std::mutex> lk(g_partner_mu);
+    auto it = g_partner.find(st);
+    if (it != g_partner.end()) {
+        *out = it->second;
+        return PRISM_OK;
+    }
+    hipStream_t p = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&p, hipStreamNonBlocking));
+    g_partner[st] = p;
+    *out = p;
+    return PRISM_OK;
+}
+
+// RAII pair of events that make `b` start after work on `a` and `a` end after `b`.
+struct ForkJoin {
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~ForkJoin() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    }
+};
+
+int prism_set_build_streams(int32_t n) {
+    if (n != 1 && n != 2) return fail(PRISM_E_INVAL, "build streams must be 1 or 2");
+    g_build_streams.store(n);
+    return PRISM_OK;
+}
+
 int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, void* ws, size_t ws_bytes,
                         void* stream) {
     int rc = check_desc(d);
@@ -536,19 +579,56 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     const PropTables tb = pd.tables();
     HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(V, T, (int64_t)nsl * n * n, (float)d->sigma, st); }));
     float2* Sout = static_cast<float2*>(S);
-    for (int b0 = 0; b0 < B; b0 += NB) {
-        const int nb = std::min(NB, B - b0);
-        const int2* bb = d_beams + b0;
+    const size_t item_w = (size_t)(n / 2) * wave_col_stride(n), layer = (size_t)(n / 2) * (n / 2);
+    // items [i0, i0 + cnt) of the batch starting at beam b0, all slices then the store, on stream q
+    auto run_items = [&](int b0, int i0, int cnt, hipStream_t q, hipEvent_t after_first_a) -> int {
+        float2* Wq = W + (size_t)i0 * item_w;
+        const int2* bq = d_beams + b0 + i0;
         for (int s = 0; s < nsl; ++s) {
-            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, W, T + (size_t)s * n * n, tb, bb, s == 0, nb, st); }));
-            HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
-                return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, W, tb, nullptr, nullptr, nullptr,
-                                     nullptr, 0.0, 0.f, nb, st);
+            HIP_TRY(timed(PRISM_K_PASS_A, q, [&] { return launch_pass_a(n, Wq, T + (size_t)s * n * n, tb, bq, s == 0, cnt, q); }));
+            if (s == 0 && after_first_a) HIP_TRY(hipEventRecord(after_first_a, q));
+            HIP_TRY(timed(PRISM_K_PASS_B, q, [&] {
+                return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, Wq, tb, nullptr, nullptr, nullptr,
+                                     nullptr, 0.0, 0.f, cnt, q);
             }));
         }
-        float2* Sb = Sout + (size_t)b0 * (n / 2) * (n / 2);
-        HIP_TRY(timed(PRISM_K_FINAL, st, [&] { return launch_smatrix_final(n, W, Sb, pd.tw_half, nb, st); }));
+        float2* Sq = Sout + (size_t)(b0 + i0) * layer;
+        HIP_TRY(timed(PRISM_K_FINAL, q, [&] { return launch_smatrix_final(n, Wq, Sq, pd.tw_half, cnt, q); }));
+        return PRISM_OK;
+    };
+    const bool overlap = g_build_streams.load() == 2 && std::min(NB, B) >= 2;
+    if (!overlap) {
+        for (int b0 = 0; b0 < B; b0 += NB) {
+            rc = run_items(b0, 0, std::min(NB, B - b0), st, nullptr);
+            if (rc) return rc;
+        }
+        return PRISM_OK;
     }
+    // Halves of every batch on st and on the partner stream; the partner waits
+    // for st's first row pass, then both streams run freely.  Within a batch the
+    // halves touch disjoint wave-buffer items, and each stream's next batch
+    // reuses only its own items, so the fork and the final join are the only
+    // cross-stream orderings needed.
+    hipStream_t st2 = nullptr;
+    rc = partner_stream(st, &st2);
+    if (rc) return rc;
+    ForkJoin fj;
+    HIP_TRY(hipEventCreateWithFlags(&fj.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&fj.join, hipEventDisableTiming));
+    for (int b0 = 0; b0 < B; b0 += NB) {
+        const int nb = std::min(NB, B - b0), h = nb / 2;
+        if (h > 0) {
+            rc = run_items(b0, 0, h, st, b0 == 0 ? fj.fork : nullptr);
+            if (rc) return rc;
+        } else if (b0 == 0) {
+            HIP_TRY(hipEventRecord(fj.fork, st));
+        }
+        if (b0 == 0) HIP_TRY(hipStreamWaitEvent(st2, fj.fork, 0));
+        rc = run_items(b0, h, nb - h, st2, nullptr);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipEventRecord(fj.join, st2));
+    HIP_TRY(hipStreamWaitEvent(st, fj.join, 0));
     return PRISM_OK;
 }
 

@@ -44,9 +44,6 @@ constexpr int WG = 256;      // 4 wavefronts
 #define PRISM_PASSA_TPREF 4096   // largest n whose transmission row is requested before the inverse
                                  // row transforms (measured better at n = 1024 and 2048)
 #endif
-#ifndef PRISM_PASSB_LDSDMA
-#define PRISM_PASSB_LDSDMA 0     // 1: next column prefetched by direct global->LDS loads
-#endif
 #ifndef PRISM_PASSB_DEPTH
 #define PRISM_PASSB_DEPTH 1      // columns prefetched ahead in registers (1 or 2)
 #endif
@@ -95,18 +92,23 @@ hipError_t launch_transmission(const float* V, float2* T, int64_t count, float s
 }
 
 // ------------------------------------------------------------------ pass A --
+// LDS (float2 slots) of one row-pass workgroup.
+template <int N>
+constexpr int pass_a_lds() { return RowCfg<N>::TR * RowCfg<N>::ROW + RowCfg<N>::XO; }
+
+// One row-pass workgroup: logical block blk of a launch over n_items items.
 template <int N, bool FIRST>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_WPE))) void k_pass_a(
-    float2* __restrict__ W, const float2* __restrict__ T, PropTables tb, const int2* __restrict__ beams,
-    int n_items) {
+__device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float2* __restrict__ T,
+                                             const PropTables& tb, const int2* __restrict__ beams, int n_items,
+                                             int blk, float2* smem) {
     using C = RowCfg<N>;
     using F = typename C::F;
     constexpr int L = C::L, E = C::E, LPT = C::LPT, G = C::G, TR = C::TR, ROW = C::ROW;
-    __shared__ float2 tile[TR * ROW];
-    __shared__ float2 xodd[C::XO];
+    float2* const tile = smem;
+    float2* const xodd = smem + TR * ROW;
 
-    const int item = blockIdx.x % n_items;
-    const int y0 = (blockIdx.x / n_items) * TR;
+    const int item = blk % n_items;
+    const int y0 = (blk / n_items) * TR;
     constexpr int CS = wave_col_stride(N);
     float2* Wi = W + (size_t)item * L * CS;
     const int tid = threadIdx.x;
@@ -208,6 +210,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
     for (int k = 0; k < NLD; ++k) gW[(size_t)k * JS * CS] = lds_slot(k);
 }
 
+template <int N, bool FIRST>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_WPE))) void k_pass_a(
+    float2* __restrict__ W, const float2* __restrict__ T, PropTables tb, const int2* __restrict__ beams,
+    int n_items) {
+    __shared__ float2 smem[pass_a_lds<N>()];
+    pass_a_block<N, FIRST>(W, T, tb, beams, n_items, blockIdx.x, smem);
+}
+
 template <int N>
 static hipError_t pass_a_n(float2* W, const float2* T, const PropTables& tb, const int2* beams, bool first,
                            int n_items, hipStream_t st) {
@@ -234,18 +244,31 @@ hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb
 }
 
 // ------------------------------------------------------------------ pass B --
+// LDS (float2 slots) of one column-pass workgroup.
+template <int N>
+constexpr int pass_b_lds() { return (PRISM_PASSB_ILP ? 2 : 1) * 4 * (64 / Fft<N / 2>::LPT) * Fft<N / 2>::LDS; }
+
+// Workgroups of a column-pass launch over n_items items.
 template <int N, int MODE>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_WPE))) void k_pass_b(
-    float2* __restrict__ W, PropTables tb, const float2* __restrict__ aux, float* __restrict__ inten,
-    const int* __restrict__ ky_max, const double2* __restrict__ probe_xy, double inv_L, float amp, int n_items) {
+constexpr int pass_b_blocks_per_item() {
+    constexpr int CPB = 4 * (64 / Fft<N / 2>::LPT) * PassBCols<N, MODE>::value;
+    return (N / 2 + CPB - 1) / CPB;
+}
+
+// One column-pass workgroup: logical block blk of a launch over n_items items.
+template <int N, int MODE>
+__device__ __forceinline__ void pass_b_block(float2* __restrict__ W, const PropTables& tb,
+                                             const float2* __restrict__ aux, float* __restrict__ inten,
+                                             const int* __restrict__ ky_max, const double2* __restrict__ probe_xy,
+                                             double inv_L, float amp, int n_items, int blk, float2* smem) {
     using F = Fft<N / 2>;
     constexpr int L = N / 2, E = F::E, LPT = F::LPT, G = 64 / LPT, CPB = 4 * G;
     constexpr int NB = PRISM_PASSB_ILP ? 2 : 1;
     constexpr int NC = PassBCols<N, MODE>::value;   // adjacent columns per transform group
-    __shared__ float2 xch[NB * CPB * F::LDS];
+    float2* const xch = smem;
 
-    const int item = blockIdx.x % n_items;
-    const int cb = blockIdx.x / n_items;
+    const int item = blk % n_items;
+    const int cb = blk / n_items;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane / LPT, lt = lane % LPT;
     const int j0 = (cb * CPB + wave * G + g) * NC;
@@ -305,20 +328,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
         for (int i = 0; i < E; ++i) pk[i] = tb.prop[lt + LPT * i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) pjs[c] = tb.prop[j0 + c];
-#if PRISM_PASSB_LDSDMA
-        // the next column lands straight in this wave's LDS slot (lane l of
-        // load i writes 16 bytes at float4 index 64 i + l), holding no VGPRs
-        __shared__ float4 pre[4 * 64 * E];
-        float4* const pw = pre + wave * 64 * E;
-        auto dma = [&](const float2* colp) {
-            const float4* c4 = reinterpret_cast<const float4*>(colp);
-#pragma unroll
-            for (int i = 0; i < E; ++i)
-                __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(c4 + lt + LPT * i),
-                                                 (void __attribute__((address_space(3)))*)(pw + 64 * i), 16, 0, 0);
-        };
-        dma(Wi + (size_t)j0 * wave_col_stride(N));
-#else
         // ring of DEPTH + 1 column buffers: slot c % (DEPTH + 1) holds column c
         constexpr int DEPTH = PRISM_PASSB_DEPTH;
         float4 ring[DEPTH + 1][E];
@@ -328,28 +337,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
 #pragma unroll
             for (int i = 0; i < E; ++i) ring[d][i] = c4[lt + LPT * i];
         }
-#endif
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int j = j0 + c;
             float2* col = Wi + (size_t)j * wave_col_stride(N);
             float4* col4 = reinterpret_cast<float4*>(col);
-#if PRISM_PASSB_LDSDMA
-            // this column's loads are the oldest outstanding vector memory
-            // operations; only the previous column's E stores may follow them
-            if (c == 0) __builtin_amdgcn_s_waitcnt(0x0F70);            // vmcnt(0)
-            else __builtin_amdgcn_s_waitcnt(0x0F70 | E);              // vmcnt(E)
-            wave_sync();
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const float4 v = pw[64 * i + lane];
-                e[i] = make_float2(v.x, v.y);
-                o[i] = make_float2(v.z, v.w);
-            }
-            __builtin_amdgcn_s_waitcnt(0xC07F);                        // lgkmcnt(0): slot read before refill
-            wave_sync();
-            if (c + 1 < NC) dma(col + wave_col_stride(N));
-#else
             if (c + DEPTH < NC) {
                 const float4* n4 = reinterpret_cast<const float4*>(col + DEPTH * wave_col_stride(N));
 #pragma unroll
@@ -360,7 +352,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
                 e[i] = make_float2(ring[c % (DEPTH + 1)][i].x, ring[c % (DEPTH + 1)][i].y);
                 o[i] = make_float2(ring[c % (DEPTH + 1)][i].z, ring[c % (DEPTH + 1)][i].w);
             }
-#endif
             const int kxj = j < N / 4 ? j : j - N / 2;
             if constexpr (PRISM_PASSB_ILP) {
                 F::template run2<-1>(e, o, lds, lds2, tw, lt);
@@ -401,6 +392,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
             }
         }
     }
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_WPE))) void k_pass_b(
+    float2* __restrict__ W, PropTables tb, const float2* __restrict__ aux, float* __restrict__ inten,
+    const int* __restrict__ ky_max, const double2* __restrict__ probe_xy, double inv_L, float amp, int n_items) {
+    __shared__ float2 smem[pass_b_lds<N>()];
+    pass_b_block<N, MODE>(W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, blockIdx.x, smem);
 }
 
 // Tile-staged column pass for interior slices (one transform per wavefront,

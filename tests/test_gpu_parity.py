@@ -361,3 +361,35 @@ def test_frozen_phonon_average(P):
     _sync()
     ref = O.frozen_phonon_prism(cfgs, sp, w.species, w.cell, w.dz, w.n, w.E0, w.alpha_max, 2, xy)
     _check_D(out.cpu().numpy().astype(np.float64), ref, "frozen-phonon mean")
+
+
+# ---------------------------------------------- overlapped two-stream build --
+@pytest.mark.parametrize("beam_batch", [0, 9, -1])
+def test_two_stream_build_equals_one_stream(P, beam_batch):
+    import torch
+    w, pos, sp = W.small_workload(n=128, cell=(20.0, 20.0, 8.0), n_atoms=40, f=2, seed=31)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, 2)
+    if beam_batch < 0:                                # batches of n_beams - 1 and 1 beams
+        beam_batch = d.n_beams - 1
+    say(f"S-matrix build on two streams vs one, n_beams={d.n_beams} beam_batch={beam_batch}")
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, 2, beam_batch=beam_batch)
+    try:
+        P.prism_set_build_streams(1)
+        S1 = P.prism_build_smatrix(d, V)
+        P.prism_set_build_streams(2)
+        S2 = P.prism_build_smatrix(d, V)
+        s = torch.cuda.Stream()                      # a second caller stream gets its own partner
+        with torch.cuda.stream(s):
+            S3 = P.prism_build_smatrix(d, V)
+        torch.cuda.synchronize()
+    finally:
+        P.prism_set_build_streams(2)
+    a = S1.cpu().numpy()
+    assert np.array_equal(a, S2.cpu().numpy()) and np.array_equal(a, S3.cpu().numpy())
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    beams = P.prism_beam_list(d).astype(np.int64)
+    t = O.transmission(Vref, d.sigma)
+    Pp = O.propagator(w.n, w.cell[0], d.lambda_, w.dz)
+    ref = O.smatrix_layer(t, Pp, int(beams[-1, 0]), int(beams[-1, 1]))
+    assert np.linalg.norm(a[-1] - ref) / np.linalg.norm(ref) <= TOL
