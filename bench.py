@@ -378,9 +378,10 @@ def streaming_study(args):
 
 def pmc_driver(args):
     """One launch of every kernel of the default workload at its real per-launch
-    size (the build cut to 4 slices: one first-slice and three interior launches
-    of each pass), then a plain 256 MiB copy whose byte count calibrates the
-    FETCH_SIZE / WRITE_SIZE counters."""
+    size (the build cut to 4 slices, on one stream as in the per-kernel timing:
+    one first-slice and three interior launches of each pass over all beams),
+    then a plain 256 MiB copy whose byte count calibrates the FETCH_SIZE /
+    WRITE_SIZE counters."""
     import dataclasses
 
     import torch
@@ -395,6 +396,7 @@ def pmc_driver(args):
     g = P.prism_grid_init(w4.cell, w4.dz, w4.n)
     V = P.prism_project_potential(pos, sp, w4.species, g)
     d = P.prism_smatrix_plan(g, w4.E0, w4.alpha_max, w4.f)
+    P.prism_set_build_streams(1)
     S = P.prism_build_smatrix(d, V)
     plan = P.prism_probe_plan_upload(d, W.scan_positions(w4.cell, *w4.scan))
     P.prism_probe_outputs(d, S, plan, prec)

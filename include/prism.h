@@ -167,13 +167,15 @@ int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap);
 int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S,
                         void* ws, size_t ws_bytes, void* stream);
 
-/* Streams used by prism_build_smatrix (process-wide): 2 (default) runs the two
- * halves of every beam batch on `stream` and on a partner stream that the
- * library creates once per caller stream (default priority, kept until the
- * process ends), the partner one pass behind, so that row and column passes
- * of different beams run together; the call still returns with all work
- * ordered on `stream`, and the S-matrix is identical to the one-stream
- * build.  1 runs everything on `stream`.  Errors: PRISM_E_INVAL (n not 1 or 2). */
+/* Streams used by prism_build_smatrix (process-wide), n in 1..4 (default 2):
+ * every beam batch is split into n parts, run on `stream` and on n - 1
+ * partner streams that the library creates once per caller stream (default
+ * priority, kept until the process ends), each part one row pass behind the
+ * previous one, so that row and column passes of different beams run
+ * together.  The call still returns with all work ordered on `stream`, and
+ * the S-matrix is identical to the one-stream build (n = 1).  Batches of
+ * fewer than n beams use as many streams as beams.
+ * Errors: PRISM_E_INVAL (n outside 1..4). */
 int prism_set_build_streams(int32_t n);
 
 /* ---- PRISM probe outputs (Fig. 1i-k) -------------------------------------- */

@@ -336,8 +336,9 @@ def multislice_outputs_streaming(grid: prism_grid, E0: float, alpha_max: float, 
 
 
 def prism_set_build_streams(n: int):
-    """1: the S-matrix build runs on the current stream only; 2 (default): two
-    halves of each beam batch overlap on the current and a partner stream."""
+    """Streams of the S-matrix build, 1-4 (default 2): each beam batch is split
+    into that many parts that overlap on the current stream and partner
+    streams; 1 runs everything on the current stream."""
     check(lib.prism_set_build_streams(int(n)))
 
 

@@ -513,41 +513,41 @@ int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap) {
 }
 
 // ------------------------------------------------ overlapped build streams --
-// The S-matrix build runs the two halves of each beam batch on the caller's
-// stream and on a partner stream (one per caller stream, default priority,
-// kept for the life of the process), the partner starting one pass later, so
-// that row passes (bound by VALU issue) of one half share the GPU with column
-// passes (bound by memory latency) of the other, each kernel at its own
-// occupancy.
+// The S-matrix build splits each beam batch into parts, one per stream: the
+// caller's stream and up to three partner streams (created once per caller
+// stream, default priority, kept for the life of the process).  Stream k
+// starts one row pass after stream k-1, so that row passes (bound by VALU
+// issue) of one part share the GPU with column passes (bound by memory
+// latency) of another, each kernel at its own occupancy.
+constexpr int kMaxBuildStreams = 4;
 std::atomic<int> g_build_streams{2};
 std::mutex g_partner_mu;
-std::map<hipStream_t, hipStream_t> g_partner;
+std::map<hipStream_t, std::vector<hipStream_t>> g_partner;
 
-int partner_stream(hipStream_t st, hipStream_t* out) {
+// The first `count` partner streams of st, created on first use.
+int partner_streams(hipStream_t st, int count, hipStream_t* out) {
     std::lock_guard<std::mutex> lk(g_partner_mu);
-    auto it = g_partner.find(st);
-    if (it != g_partner.end()) {
-        *out = it->second;
-        return PRISM_OK;
+    std::vector<hipStream_t>& v = g_partner[st];
+    while ((int)v.size() < count) {
+        hipStream_t p = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&p, hipStreamNonBlocking));
+        v.push_back(p);
     }
-    hipStream_t p = nullptr;
-    HIP_TRY(hipStreamCreateWithFlags(&p, hipStreamNonBlocking));
-    g_partner[st] = p;
-    *out = p;
+    for (int i = 0; i < count; ++i) out[i] = v[i];
     return PRISM_OK;
 }
 
-// RAII pair of events that make `b` start after work on `a` and `a` end after `b`.
-struct ForkJoin {
-    hipEvent_t fork = nullptr, join = nullptr;
-    ~ForkJoin() {
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
+// Events that order the build's streams, destroyed with the call.
+struct BuildEvents {
+    hipEvent_t ev[2 * kMaxBuildStreams] = {};
+    ~BuildEvents() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
 int prism_set_build_streams(int32_t n) {
-    if (n != 1 && n != 2) return fail(PRISM_E_INVAL, "build streams must be 1 or 2");
+    if (n < 1 || n > kMaxBuildStreams) return fail(PRISM_E_INVAL, "build streams must be 1 to %d", kMaxBuildStreams);
     g_build_streams.store(n);
     return PRISM_OK;
 }
@@ -596,39 +596,42 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
         HIP_TRY(timed(PRISM_K_FINAL, q, [&] { return launch_smatrix_final(n, Wq, Sq, pd.tw_half, cnt, q); }));
         return PRISM_OK;
     };
-    const bool overlap = g_build_streams.load() == 2 && std::min(NB, B) >= 2;
-    if (!overlap) {
+    const int P = std::min(g_build_streams.load(), NB);
+    if (P <= 1) {
         for (int b0 = 0; b0 < B; b0 += NB) {
             rc = run_items(b0, 0, std::min(NB, B - b0), st, nullptr);
             if (rc) return rc;
         }
         return PRISM_OK;
     }
-    // Halves of every batch on st and on the partner stream; the partner waits
-    // for st's first row pass, then both streams run freely.  Within a batch the
-    // halves touch disjoint wave-buffer items, and each stream's next batch
-    // reuses only its own items, so the fork and the final join are the only
-    // cross-stream orderings needed.
-    hipStream_t st2 = nullptr;
-    rc = partner_stream(st, &st2);
+    // Wave-buffer item i always holds beam b0 + i of the current batch, and
+    // stream k owns items [off(k), off(k + 1)) in every batch (a short last
+    // batch leaves the tail parts empty), so no two streams ever touch the
+    // same item; the forks of the first batch and the final joins are the
+    // only cross-stream orderings needed.
+    hipStream_t q[kMaxBuildStreams] = {st};
+    rc = partner_streams(st, P - 1, q + 1);
     if (rc) return rc;
-    ForkJoin fj;
-    HIP_TRY(hipEventCreateWithFlags(&fj.fork, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&fj.join, hipEventDisableTiming));
+    BuildEvents be;
+    for (int k = 0; k < 2 * P; ++k) HIP_TRY(hipEventCreateWithFlags(&be.ev[k], hipEventDisableTiming));
+    auto off = [&](int k) { return (int)((int64_t)k * NB / P); };
     for (int b0 = 0; b0 < B; b0 += NB) {
-        const int nb = std::min(NB, B - b0), h = nb / 2;
-        if (h > 0) {
-            rc = run_items(b0, 0, h, st, b0 == 0 ? fj.fork : nullptr);
-            if (rc) return rc;
-        } else if (b0 == 0) {
-            HIP_TRY(hipEventRecord(fj.fork, st));
+        const int nb = std::min(NB, B - b0);
+        for (int k = 0; k < P; ++k) {
+            const int i0 = off(k), cnt = std::min(off(k + 1), nb) - i0;
+            if (b0 == 0 && k > 0) HIP_TRY(hipStreamWaitEvent(q[k], be.ev[k - 1], 0));
+            if (cnt > 0) {
+                rc = run_items(b0, i0, cnt, q[k], b0 == 0 ? be.ev[k] : nullptr);
+                if (rc) return rc;
+            } else if (b0 == 0) {
+                HIP_TRY(hipEventRecord(be.ev[k], q[k]));
+            }
         }
-        if (b0 == 0) HIP_TRY(hipStreamWaitEvent(st2, fj.fork, 0));
-        rc = run_items(b0, h, nb - h, st2, nullptr);
-        if (rc) return rc;
     }
-    HIP_TRY(hipEventRecord(fj.join, st2));
-    HIP_TRY(hipStreamWaitEvent(st, fj.join, 0));
+    for (int k = 1; k < P; ++k) {
+        HIP_TRY(hipEventRecord(be.ev[P + k], q[k]));
+        HIP_TRY(hipStreamWaitEvent(st, be.ev[P + k], 0));
+    }
     return PRISM_OK;
 }
 

@@ -135,3 +135,13 @@ def test_one_hip_runtime_whatever_the_import_order():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_build_stream_count_validation():
+    import paper_1706_08563_amd as P
+    for bad in (0, 5, -1):
+        with pytest.raises(P.PrismError) as e:
+            P.prism_set_build_streams(bad)
+        assert e.value.code == P.PRISM_E_INVAL
+    for ok in (1, 3, 4, 2):                           # ends on the default
+        P.prism_set_build_streams(ok)

@@ -364,22 +364,22 @@ def test_frozen_phonon_average(P):
 
 
 # ---------------------------------------------- overlapped two-stream build --
-@pytest.mark.parametrize("beam_batch", [0, 9, -1])
-def test_two_stream_build_equals_one_stream(P, beam_batch):
+@pytest.mark.parametrize("streams,beam_batch", [(2, 0), (2, 9), (2, -1), (3, 7), (4, 0), (4, 10), (4, -3)])
+def test_multi_stream_build_equals_one_stream(P, streams, beam_batch):
     import torch
     w, pos, sp = W.small_workload(n=128, cell=(20.0, 20.0, 8.0), n_atoms=40, f=2, seed=31)
     g, V = _gpu_potential(P, w, pos, sp)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, 2)
-    if beam_batch < 0:                                # batches of n_beams - 1 and 1 beams
-        beam_batch = d.n_beams - 1
-    say(f"S-matrix build on two streams vs one, n_beams={d.n_beams} beam_batch={beam_batch}")
+    if beam_batch < 0:                                # a last batch of -beam_batch beams
+        beam_batch = d.n_beams + beam_batch
+    say(f"S-matrix build on {streams} streams vs one, n_beams={d.n_beams} beam_batch={beam_batch}")
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, 2, beam_batch=beam_batch)
     try:
         P.prism_set_build_streams(1)
         S1 = P.prism_build_smatrix(d, V)
-        P.prism_set_build_streams(2)
+        P.prism_set_build_streams(streams)
         S2 = P.prism_build_smatrix(d, V)
-        s = torch.cuda.Stream()                      # a second caller stream gets its own partner
+        s = torch.cuda.Stream()                      # a second caller stream gets its own partners
         with torch.cuda.stream(s):
             S3 = P.prism_build_smatrix(d, V)
         torch.cuda.synchronize()
