@@ -82,6 +82,33 @@ def test_full_synthesis_sampled_probes(P):
         assert err <= TOL
 
 
+def test_full_synthesis_2048_sampled_probes(P):
+    import torch
+    w = W.CONFIGS[3]
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    say(f"full synthesis 2048^2 f=8: {d.n_beams} beams x {d.ns}^2 seeded S operand, 256x256 probes")
+    rng = np.random.default_rng(404)
+    S = torch.empty((d.n_beams, d.ns, d.ns), dtype=torch.complex64, device="cuda")
+    for b0 in range(0, d.n_beams, 64):
+        S[b0:b0 + 64] = torch.from_numpy(W.random_complex((min(64, d.n_beams - b0), d.ns, d.ns), rng)).cuda()
+    xy = W.scan_positions(w.cell, *w.scan)
+    assert len(xy) == 65536
+    plan = P.prism_probe_plan_upload(d, xy)
+    pick = np.array([0, 1, 255, 256, 32768 + 128, 40000, 65535 - 256, 65535])
+    say("  copying S to the host for the oracle")
+    Sh = S.cpu().numpy()
+    beams = P.prism_beam_list(d).astype(np.int64)
+    ref = O.prism_outputs(Sh, beams, w.cell[0], w.n, d.lambda_, w.f, xy[pick])
+    del Sh
+    for name, prec in (("bf16x3", P.PRISM_SPLIT_BF16X3), ("fp32", P.PRISM_FP32)):
+        say(f"  {name} synthesis of 65536 probes")
+        out = P.prism_probe_outputs(d, S, plan, prec).cpu().numpy()
+        err = O.rel_err(out[pick], ref)
+        say(f"  {name}: rel err on {len(pick)} sampled probes {err:.3e}")
+        assert err <= TOL
+
+
 def test_full_multislice_sampled_probes(P):
     w = W.CONFIGS[1]
     say("full multislice 1024^2, 50 slices, sampled probes of the 64x64 scan")
