@@ -8,7 +8,8 @@
 // A transform is a sequence of radix-R Stockham (autosort, decimation in
 // time) stages computed in registers; consecutive stages exchange data
 // through an LDS buffer private to the wavefront, so no workgroup barrier is
-// needed.  Input and output are both in natural order, which lets callers
+// needed (FftT with SPAN = 2 spreads one transform over two wavefronts and
+// orders its exchanges with workgroup barriers instead).  Input and output are both in natural order, which lets callers
 // load and store straight from/to coalesced global memory.
 //
 // Transforms are unnormalised in both directions (DIR = -1 forward
@@ -130,12 +131,20 @@ template <> struct Plan<256>  { static constexpr int E = 8,  NST = 3; static con
 template <> struct Plan<512>  { static constexpr int E = 8,  NST = 3; static constexpr int R[3] = {8, 8, 8}; };
 template <> struct Plan<1024> { static constexpr int E = 16, NST = 3; static constexpr int R[3] = {16, 8, 8}; };
 
-template <int L>
-struct Fft {
-    static constexpr int E = Plan<L>::E;
-    static constexpr int NST = Plan<L>::NST;
-    static constexpr int LPT = L / E;                 // lanes per transform (<= 64)
-    static_assert(LPT <= 64, "one transform must fit in a wavefront");
+// Plans of transforms spread over two wavefronts of a workgroup (fewer
+// registers per lane than the one-wavefront plan of the same length).
+template <int L> struct Plan2;
+template <> struct Plan2<1024> { static constexpr int E = 8, NST = 4; static constexpr int R[4] = {8, 8, 4, 4}; };
+
+// SPAN wavefronts own one transform: SPAN = 1 synchronises a stage exchange
+// within the wavefront; SPAN = 2 uses workgroup barriers, so every wavefront
+// of the workgroup must run the same sequence of transforms.
+template <int L, class PL = Plan<L>, int SPAN = 1>
+struct FftT {
+    static constexpr int E = PL::E;
+    static constexpr int NST = PL::NST;
+    static constexpr int LPT = L / E;                 // lanes per transform
+    static_assert(SPAN == 1 ? LPT <= 64 : LPT == 64 * SPAN, "a transform spans a whole number of wavefronts");
     // Exchange buffers insert one pad slot every 2^PADSH elements, which
     // spreads the strided stage writes over the LDS banks: one slot every 8
     // elements (measured best for the 512-point passes), or every 16 for the
@@ -146,13 +155,21 @@ struct Fft {
     static constexpr int PADSH = ((PRISM_PAD16_MASK) >> __builtin_ctz(L)) & 1 ? 4 : 3;
     static constexpr int LDS = L + (L >> PADSH);      // padded exchange buffer (float2)
 
-    static constexpr int radix(int s) { return Plan<L>::R[s]; }
+    static constexpr int radix(int s) { return PL::R[s]; }
     static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
     // twiddle registers per lane: for stages s >= 1, (E/R) work items x (R-1)
     static constexpr int tw_off(int s) { return s <= 1 ? 0 : tw_off(s - 1) + (E / radix(s - 1)) * (radix(s - 1) - 1); }
     static constexpr int NTW = tw_off(NST) > 0 ? tw_off(NST) : 1;
 
     __device__ __forceinline__ static int pad(int i) { return i + (i >> PADSH); }
+
+    // Ordering of exchange-buffer traffic among the lanes of one transform.
+    __device__ __forceinline__ static void sync() {
+        if constexpr (SPAN == 1)
+            wave_sync();
+        else
+            __syncthreads();
+    }
 
     // Forward twiddles of this lane, read from W_L[m] = e^{-2 pi i m / L}.
     struct Twiddles {
@@ -207,7 +224,7 @@ struct Fft {
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[u + r * U] = out[u * R + r];
         } else {
-            wave_sync();
+            sync();
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 int j = lt + LPT * u;
@@ -215,7 +232,7 @@ struct Fft {
 #pragma unroll
                 for (int r = 0; r < R; ++r) lds(base + r * NS) = out[u * R + r];
             }
-            wave_sync();
+            sync();
 #pragma unroll
             for (int i = 0; i < E; ++i) v[i] = lds(lt + LPT * i);
             stage<DIR, S + 1>(v, lds, tw, lt);
@@ -262,7 +279,7 @@ struct Fft {
                     v2[u + r * U] = o2[u * R + r];
                 }
         } else {
-            wave_sync();
+            sync();
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 int j = lt + LPT * u;
@@ -273,7 +290,7 @@ struct Fft {
                     x2(base + r * NS) = o2[u * R + r];
                 }
             }
-            wave_sync();
+            sync();
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 v1[i] = x1(lt + LPT * i);
@@ -297,5 +314,8 @@ struct Fft {
         stage<DIR, 0>(v, RowX{lds}, tw, lt);
     }
 };
+
+template <int L>
+using Fft = FftT<L, Plan<L>, 1>;
 
 }  // namespace prism

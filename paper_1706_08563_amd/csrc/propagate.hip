@@ -41,8 +41,9 @@ constexpr int WG = 256;      // 4 wavefronts
 #define PRISM_PASSB_WPE 1
 #endif
 #ifndef PRISM_PASSA_TPREF
-#define PRISM_PASSA_TPREF 4096   // largest n whose transmission row is requested before the inverse
-                                 // row transforms (measured better at n = 1024 and 2048)
+#define PRISM_PASSA_TPREF 1024   // largest n whose transmission row is requested before the inverse
+                                 // row transforms (measured better at n = 1024; at 2048 the same
+                                 // time, and holding the row there spills registers)
 #endif
 #ifndef PRISM_PASSB_DEPTH
 #define PRISM_PASSB_DEPTH 1      // columns prefetched ahead in registers (1 or 2)
@@ -59,18 +60,36 @@ struct PassBCols {
         (MODE != PASSB_INIT && (N / 2) % (CPB * PRISM_PASSB_COLS) == 0) ? PRISM_PASSB_COLS : 1;
 };
 
+// Transforms of length L = n/2 spread over SPAN wavefronts.  The row pass and
+// the tiled column pass use two wavefronts per 1024-point transform: the
+// one-wavefront plan holds 16 elements per lane and needs more than 256
+// registers, i.e. one wave per SIMD.
+#ifndef PRISM_SPAN2_MIN
+#define PRISM_SPAN2_MIN 2048     // smallest n whose row and tiled column passes use two-wavefront transforms
+#endif
+template <int L, int SPAN>
+struct FftFor { using type = Fft<L>; };
+template <>
+struct FftFor<1024, 2> { using type = FftT<1024, Plan2<1024>, 2>; };
 template <int N>
+constexpr int pass_span() { return (N / 2 == 1024 && N >= PRISM_SPAN2_MIN) ? 2 : 1; }
+
+template <int N, int SPAN = 1>
 struct RowCfg {
     static constexpr int L = N / 2;
-    using F = Fft<L>;
+    using F = typename FftFor<L, SPAN>::type;
     static constexpr int E = F::E;
     static constexpr int LPT = F::LPT;
-    static constexpr int G = 64 / LPT;                       // transforms per wave at once
+    static constexpr int G = LPT <= 64 ? 64 / LPT : 1;       // transforms per wave at once (SPAN = 1)
+    static constexpr int TPW = WG / LPT;                     // transforms per workgroup at once
     static constexpr int TR0 = (N <= 1024) ? PRISM_PASSA_ROWS : PRISM_PASSA_ROWS / 2;
-    static constexpr int TR = TR0 > 4 * G ? TR0 : 4 * G;     // rows per workgroup (tile height)
+    static constexpr int TR = TR0 > TPW ? TR0 : TPW;         // rows per workgroup (tile height)
     static constexpr int ROW = F::LDS + 1;                   // odd LDS row stride (float2)
-    static constexpr int XO = PRISM_PASSA_ILP ? 4 * G * F::LDS : 1;   // odd-transform buffers
+    static constexpr int XO = PRISM_PASSA_ILP ? TPW * F::LDS : 1;   // odd-transform buffers
 };
+// Row-pass configuration.
+template <int N>
+using RowCfgA = RowCfg<N, pass_span<N>()>;
 
 // ------------------------------------------------------------ transmission --
 __global__ __launch_bounds__(WG) void k_transmission(const float* __restrict__ V, float2* __restrict__ T,
@@ -94,16 +113,16 @@ hipError_t launch_transmission(const float* V, float2* T, int64_t count, float s
 // ------------------------------------------------------------------ pass A --
 // LDS (float2 slots) of one row-pass workgroup.
 template <int N>
-constexpr int pass_a_lds() { return RowCfg<N>::TR * RowCfg<N>::ROW + RowCfg<N>::XO; }
+constexpr int pass_a_lds() { return RowCfgA<N>::TR * RowCfgA<N>::ROW + RowCfgA<N>::XO; }
 
 // One row-pass workgroup: logical block blk of a launch over n_items items.
 template <int N, bool FIRST>
 __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float2* __restrict__ T,
                                              const PropTables& tb, const int2* __restrict__ beams, int n_items,
                                              int blk, float2* smem) {
-    using C = RowCfg<N>;
+    using C = RowCfgA<N>;
     using F = typename C::F;
-    constexpr int L = C::L, E = C::E, LPT = C::LPT, G = C::G, TR = C::TR, ROW = C::ROW;
+    constexpr int L = C::L, E = C::E, LPT = C::LPT, TPW = C::TPW, TR = C::TR, ROW = C::ROW;
     float2* const tile = smem;
     float2* const xodd = smem + TR * ROW;
 
@@ -136,8 +155,8 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
         __syncthreads();
     }
 
-    const int wave = tid >> 6, lane = tid & 63;
-    const int g = lane / LPT, lt = lane % LPT;
+    // transform tix of the workgroup (row yy = tix, tix + TPW, ...), lane lt of it
+    const int tix = tid / LPT, lt = tid % LPT;
     typename F::Twiddles tw;
     tw.load(tb.tw_half, lt);
     float2 btw[E];
@@ -150,8 +169,8 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
         ky = k.y;
     }
 
-    for (int r0 = wave * G; r0 < TR; r0 += 4 * G) {
-        const int yy = r0 + g, y = y0 + yy;
+    for (int yy = tix; yy < TR; yy += TPW) {      // the same trip count for every wavefront
+        const int y = y0 + yy;
         float2* row = tile + yy * ROW;
         // transmission of this row, requested before the inverse transforms
         // so the load latency hides behind them
@@ -180,7 +199,7 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
                 o[i] = cmulc(e[i], btw[i]);
             }
             if constexpr (PRISM_PASSA_ILP) {
-                F::template run2<+1>(e, o, row, xodd + (wave * G + g) * F::LDS, tw, lt);
+                F::template run2<+1>(e, o, row, xodd + tix * F::LDS, tw, lt);
             } else {
                 F::template run<+1>(e, row, tw, lt);
                 F::template run<+1>(o, row, tw, lt);
@@ -196,12 +215,12 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
             o[i] = cmul(o[i], make_float2(trow[i].z, trow[i].w));
         }
         if constexpr (PRISM_PASSA_ILP) {
-            F::template run2<-1>(e, o, row, xodd + (wave * G + g) * F::LDS, tw, lt);
+            F::template run2<-1>(e, o, row, xodd + tix * F::LDS, tw, lt);
         } else {
             F::template run<-1>(e, row, tw, lt);
             F::template run<-1>(o, row, tw, lt);
         }
-        wave_sync();
+        F::sync();
 #pragma unroll
         for (int i = 0; i < E; ++i) row[F::pad(lt + LPT * i)] = cadd(e[i], cmul(btw[i], o[i]));
     }
@@ -210,8 +229,13 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
     for (int k = 0; k < NLD; ++k) gW[(size_t)k * JS * CS] = lds_slot(k);
 }
 
+// Waves per SIMD asked of the register allocator: two for the two-wavefront
+// transforms (whose registers fit that budget), PRISM_PASSA_WPE otherwise.
+template <int N>
+constexpr int pass_a_wpe() { return pass_span<N>() == 2 ? 2 : PRISM_PASSA_WPE; }
+
 template <int N, bool FIRST>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_WPE))) void k_pass_a(
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass_a_wpe<N>()))) void k_pass_a(
     float2* __restrict__ W, const float2* __restrict__ T, PropTables tb, const int2* __restrict__ beams,
     int n_items) {
     __shared__ float2 smem[pass_a_lds<N>()];
@@ -221,7 +245,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSA_
 template <int N>
 static hipError_t pass_a_n(float2* W, const float2* T, const PropTables& tb, const int2* beams, bool first,
                            int n_items, hipStream_t st) {
-    constexpr int TR = RowCfg<N>::TR;
+    constexpr int TR = RowCfgA<N>::TR;
     dim3 grid((unsigned)((size_t)n_items * (N / TR)));
     if (first)
         hipLaunchKernelGGL((k_pass_a<N, true>), grid, dim3(WG), 0, st, W, T, tb, beams, n_items);
@@ -413,23 +437,25 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
 #endif
 template <int N>
 struct PassBTile {
-    using F = Fft<N / 2>;
+    using F = typename FftFor<N / 2, pass_span<N>()>::type;
     // measured: 2.08 -> 2.23 ms at n = 1024 (slower), 24.6 -> 16.4 ms at n = 2048
-    static constexpr bool ok = F::LPT == 64 && N >= PRISM_PASSB_TILE_MIN;   // one transform per wavefront
+    static constexpr bool ok = (F::LPT == 64 || F::LPT == 128) && N >= PRISM_PASSB_TILE_MIN;
     static constexpr int TC = N <= 1024 ? 8 : 4;               // columns per workgroup
     static constexpr int CS = 2 * F::LDS;                     // LDS slots per column (e and o buffers)
+    static constexpr int TPW = WG / F::LPT;                   // columns transformed at once
 };
 
 template <int N>
 __global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, PropTables tb, int n_items) {
     using T = PassBTile<N>;
     using F = typename T::F;
-    constexpr int L = N / 2, E = F::E, LPT = F::LPT, TC = T::TC, CS = T::CS;
-    static_assert(LPT == 64, "one transform per wavefront");
+    constexpr int L = N / 2, E = F::E, LPT = F::LPT, TC = T::TC, CS = T::CS, TPW = T::TPW;
+    static_assert(LPT == 64 || LPT == 128, "one or two wavefronts per transform");
+    static_assert(TC % TPW == 0, "the same column count for every wavefront");
     __shared__ float2 tile[TC * CS];
     const int item = blockIdx.x % n_items;
     const int jb = (blockIdx.x / n_items) * TC;
-    const int tid = threadIdx.x, wave = tid >> 6, lt = tid & 63;
+    const int tid = threadIdx.x, tix = tid / LPT, lt = tid % LPT;
     float2* const Wi = W + (size_t)item * L * wave_col_stride(N);
     {
         // column c, float4 m = rows (2m, 2m+1): even sample to buffer 0, odd to buffer 1
@@ -458,7 +484,7 @@ __global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, Prop
     }
     __syncthreads();
 #pragma unroll 1
-    for (int c = wave; c < TC; c += 4) {
+    for (int c = tix; c < TC; c += TPW) {
         const int j = jb + c;
         float2* const xe = tile + c * CS;
         float2* const xo = xe + F::LDS;
