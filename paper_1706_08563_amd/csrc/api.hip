@@ -615,24 +615,35 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     BuildEvents be;
     for (int k = 0; k < 2 * P; ++k) HIP_TRY(hipEventCreateWithFlags(&be.ev[k], hipEventDisableTiming));
     auto off = [&](int k) { return (int)((int64_t)k * NB / P); };
-    for (int b0 = 0; b0 < B; b0 += NB) {
-        const int nb = std::min(NB, B - b0);
-        for (int k = 0; k < P; ++k) {
-            const int i0 = off(k), cnt = std::min(off(k + 1), nb) - i0;
-            if (b0 == 0 && k > 0) HIP_TRY(hipStreamWaitEvent(q[k], be.ev[k - 1], 0));
-            if (cnt > 0) {
-                rc = run_items(b0, i0, cnt, q[k], b0 == 0 ? be.ev[k] : nullptr);
-                if (rc) return rc;
-            } else if (b0 == 0) {
-                HIP_TRY(hipEventRecord(be.ev[k], q[k]));
+    int forked = 1;                              // streams that may hold work of this call
+    auto enqueue = [&]() -> int {
+        for (int b0 = 0; b0 < B; b0 += NB) {
+            const int nb = std::min(NB, B - b0);
+            for (int k = 0; k < P; ++k) {
+                const int i0 = off(k), cnt = std::min(off(k + 1), nb) - i0;
+                if (b0 == 0 && k > 0) {
+                    HIP_TRY(hipStreamWaitEvent(q[k], be.ev[k - 1], 0));
+                    forked = k + 1;
+                }
+                if (cnt > 0) {
+                    int r = run_items(b0, i0, cnt, q[k], b0 == 0 ? be.ev[k] : nullptr);
+                    if (r) return r;
+                } else if (b0 == 0) {
+                    HIP_TRY(hipEventRecord(be.ev[k], q[k]));
+                }
             }
         }
+        return PRISM_OK;
+    };
+    rc = enqueue();
+    // join every partner that may hold work, also after an error, so that
+    // the caller's stream orders all of this call's work
+    for (int k = 1; k < forked; ++k) {
+        hipError_t e = hipEventRecord(be.ev[P + k], q[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, be.ev[P + k], 0);
+        if (e != hipSuccess && rc == PRISM_OK) rc = fail(PRISM_E_DEVICE, "build: stream join: %s", hipGetErrorString(e));
     }
-    for (int k = 1; k < P; ++k) {
-        HIP_TRY(hipEventRecord(be.ev[P + k], q[k]));
-        HIP_TRY(hipStreamWaitEvent(st, be.ev[P + k], 0));
-    }
-    return PRISM_OK;
+    return rc;
 }
 
 // -------------------------------------------------------- probe outputs --
