@@ -63,6 +63,26 @@ def recorded_traffic(kernel, workload):
         return None
 
 
+def copy_bandwidth(gib=2, reps=5):
+    """Bytes read + written per second by a plain device-to-device copy of
+    `gib` GiB (torch's copy kernel), the practical HBM ceiling next to the
+    8 TB/s peak."""
+    import torch
+    x = torch.ones(gib << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * x.numel() * 4 * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def pass_flops(n, B, rows):
     """Algorithmic FP32 flops of one propagation-pass launch over B beams:
     `rows` lines of two inverse and two forward (n/2)-point complex FFTs
@@ -85,10 +105,11 @@ def parse():
     ap.add_argument("--cpu-beams", type=int, default=3)
     ap.add_argument("--cpu-probes", type=int, default=12)
     ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson stream of mixed requests)")
-    ap.add_argument("--requests", type=int, default=40)
+    ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--loads", default="0.4,0.8,1.6",
                     help="offered loads, as fractions of the capacity measured by a saturation run")
-    ap.add_argument("--grids", default="256,512,1024,2048")
+    ap.add_argument("--grids", default="256,512,1024",
+                    help="grid sizes of the serving requests (2048 adds builds of tens of seconds)")
     ap.add_argument("--precision-study", action="store_true", help="2048^2 f=8 contraction precision study")
     ap.add_argument("--streaming-study", action="store_true",
                     help="single-transfer vs streaming memory model on the default workload: time and peak HBM")
@@ -569,6 +590,7 @@ def main():
         "probe_plan_host_s": plan_s,
         "kernels": kernels,
         "roofline": roof,
+        "hbm_copy_GB_per_s": copy_bandwidth(),
     }
     res["multislice"] = multislice_leg(args)
     if not args.no_cpu_baseline:
