@@ -374,6 +374,13 @@ int prism_timing_reset(void);
  * last reset; waits for the recorded events.  Errors: PRISM_E_INVAL, PRISM_E_DEVICE. */
 int prism_timing_read(int32_t cls, double* total_ms, int64_t* launches);
 
+/* Diagnostic: copies `bytes` (a multiple of 16) from src to dst (device,
+ * 16-byte aligned, not overlapping) with one 16-byte load and store per
+ * thread, the plain streaming pattern that calibrates the HBM bandwidth the
+ * propagation passes are compared with.  Enqueued on `stream`.
+ * Errors: PRISM_E_INVAL, PRISM_E_DEVICE. */
+int prism_device_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* prism_last_error(void);
 

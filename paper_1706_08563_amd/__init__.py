@@ -19,5 +19,6 @@ from .api import (  # noqa: F401
     prism_streaming_build_workspace, prism_build_smatrix_streaming, prism_probe_streaming_workspace,
     prism_probe_outputs_streaming, multislice_streaming_workspace, multislice_outputs_streaming,
     prism_probe_chunked_workspace, prism_probe_outputs_chunked, prism_set_build_streams,
+    prism_device_copy,
 )
 from . import _lib  # noqa: F401

@@ -107,6 +107,7 @@ _SIGNATURES = {
                                       c_void_p, c_void_p], c_int32),
     "prism_detector_bin_map": ([c_double, c_double, c_double, c_double, c_int32, c_int32, c_void_p], c_int32),
     "prism_set_build_streams": ([c_int32], c_int32),
+    "prism_device_copy": ([c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "prism_timing_enable": ([c_int32], c_int32),
     "prism_timing_reset": ([], c_int32),
     "prism_timing_read": ([c_int32, POINTER(c_double), POINTER(c_int64)], c_int32),

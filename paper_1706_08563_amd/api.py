@@ -342,6 +342,15 @@ def prism_set_build_streams(n: int):
     check(lib.prism_set_build_streams(int(n)))
 
 
+def prism_device_copy(src, dst):
+    """Copy tensor src into dst (same byte size, multiple of 16) with the
+    library's plain streaming copy kernel on the current stream."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("prism_device_copy: size mismatch")
+    check(lib.prism_device_copy(_dev(src), _dev(dst), nbytes, _stream()))
+
+
 # ---------------------------------------------------------------- timing --
 def prism_timing_enable(enable: bool = True):
     check(lib.prism_timing_enable(1 if enable else 0))

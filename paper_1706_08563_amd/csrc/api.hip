@@ -1343,6 +1343,27 @@ int prism_probe_outputs_chunked(const prism_smatrix_desc* d, const void* S, cons
                          nullptr, false);
 }
 
+// ------------------------------------------------------------ diagnostics --
+__global__ __launch_bounds__(256) void k_copy16(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                size_t n) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+int prism_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+        return fail(PRISM_E_INVAL, "copy: NULL, misaligned or not a multiple of 16 bytes");
+    const uintptr_t s0 = (uintptr_t)src, d0 = (uintptr_t)dst;
+    if (s0 < d0 + bytes && d0 < s0 + bytes) return fail(PRISM_E_INVAL, "copy: overlapping buffers");
+    const size_t n = bytes / 16;
+    if (n == 0) return PRISM_OK;
+    if ((n + 255) / 256 > 0x7fffffffu) return fail(PRISM_E_INVAL, "copy: too large");
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream),
+                       static_cast<const float4*>(src), static_cast<float4*>(dst), n);
+    HIP_TRY(hipGetLastError());
+    return PRISM_OK;
+}
+
 int prism_timing_enable(int32_t enable) {
     t_timing = enable != 0;
     return PRISM_OK;

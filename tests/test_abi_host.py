@@ -145,3 +145,18 @@ def test_build_stream_count_validation():
         assert e.value.code == P.PRISM_E_INVAL
     for ok in (1, 3, 4, 2):                           # ends on the default
         P.prism_set_build_streams(ok)
+
+
+def test_device_copy_argument_checks():
+    import ctypes
+    import paper_1706_08563_amd as P
+    lib = P.lib
+    buf = ctypes.create_string_buffer(64)
+    base = ctypes.addressof(buf)
+    aligned = (base + 15) // 16 * 16
+    # rejected on the host before any device work: NULL, size, alignment, overlap
+    assert lib.prism_device_copy(None, ctypes.c_void_p(aligned), 16, None) == P.PRISM_E_INVAL
+    assert lib.prism_device_copy(ctypes.c_void_p(aligned), ctypes.c_void_p(aligned + 16), 8, None) == P.PRISM_E_INVAL
+    assert lib.prism_device_copy(ctypes.c_void_p(aligned + 4), ctypes.c_void_p(aligned + 32), 16, None) == P.PRISM_E_INVAL
+    assert lib.prism_device_copy(ctypes.c_void_p(aligned), ctypes.c_void_p(aligned + 16), 32, None) == P.PRISM_E_INVAL
+    assert lib.prism_device_copy(ctypes.c_void_p(aligned), ctypes.c_void_p(aligned + 16), 0, None) == P.PRISM_OK

@@ -393,3 +393,14 @@ def test_multi_stream_build_equals_one_stream(P, streams, beam_batch):
     Pp = O.propagator(w.n, w.cell[0], d.lambda_, w.dz)
     ref = O.smatrix_layer(t, Pp, int(beams[-1, 0]), int(beams[-1, 1]))
     assert np.linalg.norm(a[-1] - ref) / np.linalg.norm(ref) <= TOL
+
+
+# -------------------------------------------------------- diagnostic copy --
+def test_device_copy(P):
+    import torch
+    say("diagnostic streaming copy, ragged size")
+    x = torch.randn(1000004, device="cuda")             # 4,000,016 bytes: 250,001 16-byte chunks
+    y = torch.zeros_like(x)
+    P.prism_device_copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
