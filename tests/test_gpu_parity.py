@@ -182,6 +182,21 @@ def test_multislice_end_to_end_small(P, n, scan, seed):
     _check_D(out.cpu().numpy().astype(np.float64), ref, "multislice")
 
 
+def test_multislice_2048_two_wavefront_passes(P):
+    """n = 2048: the row pass and the tiled column pass spread each 1024-point
+    transform over two wavefronts; 3 probes (odd batch) over 3 slices."""
+    say("multislice n=2048 S=3, 3 probes (two-wavefront transforms)")
+    w, pos, sp = W.small_workload(n=2048, cell=(200.0, 200.0, 6.0), n_atoms=400, scan=(3, 1), seed=21)
+    g, V = _gpu_potential(P, w, pos, sp)
+    xy = np.array([[0.0, 0.0], [101.3, 57.9], [210.5, -3.2]])
+    out = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=3)
+    _sync()
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    ref = O.multislice_outputs(Vref, w.cell[0], w.dz, O.wavelength(w.E0), O.interaction_constant(w.E0),
+                               w.alpha_max, xy)
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "multislice n=2048")
+
+
 def test_prism_f1_matches_oracle_multislice(P):
     say("prism f=1 vs oracle multislice n=64")
     w, pos, sp = W.small_workload(n=64, n_atoms=16, seed=5, f=1)
