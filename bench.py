@@ -102,7 +102,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp32", "bf16x3", "bf16"], default="bf16x3")
-    ap.add_argument("--config", type=int, default=2, help="workload index (2: PRISM f=4 @1024^2)")
+    ap.add_argument("--workload", default="prism_f4_np_1024",
+                    choices=["prism_f4_np_1024", "prism_f8_np_2048", "prism_f2_sc_256"],
+                    help="PRISM workload (default: f = 4 at 1024^2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-beams", type=int, default=3)
     ap.add_argument("--cpu-probes", type=int, default=12)
@@ -263,7 +265,7 @@ def multislice_leg(args):
     import paper_1706_08563_amd as P
     import workloads as W
 
-    w = W.CONFIGS[1]
+    w = W.WORKLOADS["multislice_np_1024"]
     pos, sp = W.atoms_for(w)
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     V = P.prism_project_potential(pos, sp, w.species, g)
@@ -305,7 +307,7 @@ def precision_study(args):
     import paper_1706_08563_amd as P
     import workloads as W
 
-    w = W.CONFIGS[3]
+    w = W.WORKLOADS["prism_f8_np_2048"]
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
     rng = np.random.default_rng(303)
@@ -359,7 +361,7 @@ def streaming_study(args):
     import workloads as W
 
     prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
-    w = W.CONFIGS[args.config]
+    w = W.WORKLOADS[args.workload]
     pos, sp = W.atoms_for(w)
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     V = P.prism_project_potential(pos, sp, w.species, g)
@@ -413,7 +415,7 @@ def pmc_driver(args):
     import workloads as W
 
     prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
-    w = W.CONFIGS[args.config]
+    w = W.WORKLOADS[args.workload]
     w4 = dataclasses.replace(w, cell=(w.cell[0], w.cell[1], 4 * w.dz))
     pos, sp = W.atoms_for(w4)
     g = P.prism_grid_init(w4.cell, w4.dz, w4.n)
@@ -433,7 +435,7 @@ def pmc_driver(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this implementation runs on a single GPU; --gpus must be 1",
                           "detail": "multi-GPU sharding is described in the design notes, not implemented"}))
         sys.exit(2)
     if args.serve:
@@ -460,7 +462,7 @@ def main():
     torch.cuda.set_device(dev)
     prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
 
-    w = W.CONFIGS[args.config]
+    w = W.WORKLOADS[args.workload]
     log(f"workload {w.name}: setup")
     pos, sp = W.atoms_for(w)
     g = P.prism_grid_init(w.cell, w.dz, w.n)

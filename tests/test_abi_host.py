@@ -62,10 +62,10 @@ def test_smatrix_plan_validation_codes():
         assert e.value.code == code, args
 
 
-@pytest.mark.parametrize("cfg", [0, 2, 3])
+@pytest.mark.parametrize("cfg", ["prism_f2_sc_256", "prism_f4_np_1024", "prism_f8_np_2048"])
 def test_plan_constants_and_beams_match_oracle(cfg):
     P = _lib()
-    w = W.CONFIGS[cfg]
+    w = W.WORKLOADS[cfg]
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
     lam = O.wavelength(w.E0)
@@ -78,10 +78,12 @@ def test_plan_constants_and_beams_match_oracle(cfg):
     assert d.m_win == w.n // 2 // w.f
 
 
-@pytest.mark.parametrize("m,f,cfg", [(64, 2, 0), (128, 4, 2), (128, 8, 3), (256, 1, 0), (1024, 1, 1)])
+@pytest.mark.parametrize("m,f,cfg", [(64, 2, "prism_f2_sc_256"), (128, 4, "prism_f4_np_1024"),
+                                      (128, 8, "prism_f8_np_2048"), (256, 1, "prism_f2_sc_256"),
+                                      (1024, 1, "multislice_np_1024")])
 def test_bin_map_bit_exact(m, f, cfg):
     P = _lib()
-    w = W.CONFIGS[cfg]
+    w = W.WORKLOADS[cfg]
     L = w.cell[0]
     lam = O.wavelength(w.E0)
     a_aa = O.alpha_aa(lam, w.n, L)
@@ -103,7 +105,7 @@ def test_bin_map_edges_and_explicit_bin_count():
 
 def test_probe_plan_sizes():
     P = _lib()
-    w = W.CONFIGS[0]
+    w = W.WORKLOADS["prism_f2_sc_256"]
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
     xy = W.scan_positions(w.cell, *w.scan)

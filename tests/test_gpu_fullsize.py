@@ -40,10 +40,10 @@ def _potentials(P, w):
     return g, V, Vref
 
 
-@pytest.mark.parametrize("cfg", [2, 3])
+@pytest.mark.parametrize("cfg", ["prism_f4_np_1024", "prism_f8_np_2048"])
 def test_full_smatrix_sampled_layers(P, cfg):
     import torch
-    w = W.CONFIGS[cfg]
+    w = W.WORKLOADS[cfg]
     say(f"full S-matrix {w.name}: build on GPU, sampled layers vs oracle")
     g, V, Vref = _potentials(P, w)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
@@ -52,7 +52,7 @@ def test_full_smatrix_sampled_layers(P, cfg):
     beams = P.prism_beam_list(d)
     t = O.transmission(Vref, d.sigma)
     Pp = O.propagator(w.n, w.cell[0], d.lambda_, w.dz)
-    sample = (0, 311, len(beams) // 2, len(beams) - 1) if cfg == 2 else (0, len(beams) // 2 + 7)
+    sample = (0, 311, len(beams) // 2, len(beams) - 1) if cfg == "prism_f4_np_1024" else (0, len(beams) // 2 + 7)
     for b in sample:
         ref = O.smatrix_layer(t, Pp, int(beams[b, 0]), int(beams[b, 1]))
         got = S[b].cpu().numpy().astype(np.complex128)
@@ -63,7 +63,7 @@ def test_full_smatrix_sampled_layers(P, cfg):
 
 def test_full_synthesis_sampled_probes(P):
     import torch
-    w = W.CONFIGS[2]
+    w = W.WORKLOADS["prism_f4_np_1024"]
     say("full synthesis 1024^2 f=4, 128x128 probes, seeded S operand")
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
@@ -84,7 +84,7 @@ def test_full_synthesis_sampled_probes(P):
 
 def test_full_synthesis_2048_sampled_probes(P):
     import torch
-    w = W.CONFIGS[3]
+    w = W.WORKLOADS["prism_f8_np_2048"]
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
     say(f"full synthesis 2048^2 f=8: {d.n_beams} beams x {d.ns}^2 seeded S operand, 256x256 probes")
@@ -110,7 +110,7 @@ def test_full_synthesis_2048_sampled_probes(P):
 
 
 def test_full_multislice_sampled_probes(P):
-    w = W.CONFIGS[1]
+    w = W.WORKLOADS["multislice_np_1024"]
     say("full multislice 1024^2, 50 slices, sampled probes of the 64x64 scan")
     g, V, Vref = _potentials(P, w)
     xy = W.scan_positions(w.cell, *w.scan)

@@ -59,9 +59,9 @@ def test_potential_parity_small(P, n, cell, n_atoms, seed):
     assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
-def test_potential_parity_config0(P):
-    say("potential config0 256^2")
-    w = W.CONFIGS[0]
+def test_potential_parity_prism_f2_sc_256(P):
+    say("potential prism_f2_sc_256 (256^2)")
+    w = W.WORKLOADS["prism_f2_sc_256"]
     pos, sp = W.atoms_for(w)
     g, V = _gpu_potential(P, w, pos, sp)
     ref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
@@ -210,11 +210,11 @@ def test_prism_f1_matches_oracle_multislice(P):
     _check_D(out.cpu().numpy().astype(np.float64), ref, "prism f=1 vs multislice")
 
 
-# ------------------------------------------------------------------ config 0 --
-def test_config0_prism_and_multislice_full(P):
-    """Config 0 in full: PRISM f=2 (256 probes) and multislice on the same cell."""
-    say("config0 full prism f=2 + multislice")
-    w = W.CONFIGS[0]
+# ------------------------------------------------- small PRISM workload, 256^2 --
+def test_prism_f2_sc_256_prism_and_multislice_full(P):
+    """The 256^2 simple-cubic workload in full: PRISM f=2 (256 probes) and multislice on the same cell."""
+    say("prism_f2_sc_256 full: prism f=2 + multislice")
+    w = W.WORKLOADS["prism_f2_sc_256"]
     pos, sp = W.atoms_for(w)
     g, V = _gpu_potential(P, w, pos, sp)
     d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
@@ -231,10 +231,10 @@ def test_config0_prism_and_multislice_full(P):
     Sref = O.build_smatrix(Vref, L, w.dz, d.lambda_, d.sigma, beams)
     assert np.max(np.abs(Sg.cpu().numpy() - Sref)) <= TOL * np.max(np.abs(Sref))
     ref = O.prism_outputs(Sref, beams, L, w.n, d.lambda_, w.f, xy)
-    _check_D(out.cpu().numpy().astype(np.float64), ref, "config0 prism")
-    _check_D(out3.cpu().numpy().astype(np.float64), ref, "config0 prism split-bf16")
+    _check_D(out.cpu().numpy().astype(np.float64), ref, "prism_f2_sc_256 prism")
+    _check_D(out3.cpu().numpy().astype(np.float64), ref, "prism_f2_sc_256 prism split-bf16")
     mref = O.multislice_outputs(Vref, L, w.dz, d.lambda_, d.sigma, w.alpha_max, xy[::17])
-    _check_D(ms.cpu().numpy().astype(np.float64), mref, "config0 multislice")
+    _check_D(ms.cpu().numpy().astype(np.float64), mref, "prism_f2_sc_256 multislice")
 
 
 # ------------------------------------------------- batching, large sizes --

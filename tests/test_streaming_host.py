@@ -16,7 +16,7 @@ def _P():
 
 
 def _desc(P, n=1024, f=4, beam_batch=0):
-    w = W.CONFIGS[2]
+    w = W.WORKLOADS["prism_f4_np_1024"]
     g = P.prism_grid_init(w.cell, w.dz, n)
     return w, g, P.prism_smatrix_plan(g, w.E0, w.alpha_max, f, beam_batch=beam_batch)
 
@@ -97,7 +97,7 @@ def test_streaming_build_and_multislice_validation():
 def test_memory_planner_choices():
     P = _P()
     from paper_1706_08563_amd import memory as M
-    w = W.CONFIGS[2]
+    w = W.WORKLOADS["prism_f4_np_1024"]
     g = P.prism_grid_init(w.cell, w.dz, w.n)
     xy = W.scan_positions(w.cell, 32, 32)
     big = M.plan_memory(g, w.E0, w.alpha_max, w.f, xy, 1 << 40)

@@ -53,24 +53,25 @@ class Workload:
 
 
 # ---------------------------------------------------------------------------
-# Workload definitions.  Sizes follow the benchmark configurations: config 0 is
-# the small PRISM case, 1 the 1024^2 multislice case, 2 the 1024^2 PRISM f=4
-# case, 3 the 2048^2 PRISM f=8 precision case.
+# Workload definitions: a small PRISM case (256^2, f = 2, simple cubic), the
+# 1024^2 multislice case, the 1024^2 PRISM f = 4 case (the benchmark
+# workload) and the 2048^2 PRISM f = 8 case, on the nanoparticle-in-matrix
+# cell; each named by method, f, structure and grid.
 # ---------------------------------------------------------------------------
 AU = species_for_z(79)
 C = species_for_z(6)
 SC1 = Species(amp=(20.0, 5.0), width=(0.3, 0.8))
 
-CONFIGS = {
-    0: Workload("prism_f2_sc_256", (20.0, 20.0, 20.0), 256, 2.0, 80e3, 0.020, 2,
-                (16, 16), (SC1,), seed=0, structure="sc"),
-    1: Workload("multislice_np_1024", (100.0, 100.0, 100.0), 1024, 2.0, 200e3, 0.020, 0,
-                (64, 64), (AU, C), seed=1, structure="np"),
-    2: Workload("prism_f4_np_1024", (100.0, 100.0, 100.0), 1024, 2.0, 200e3, 0.020, 4,
-                (128, 128), (AU, C), seed=2, structure="np"),
-    3: Workload("prism_f8_np_2048", (200.0, 200.0, 100.0), 2048, 2.0, 200e3, 0.020, 8,
-                (256, 256), (AU, C), seed=3, structure="np"),
-}
+WORKLOADS = {w.name: w for w in (
+    Workload("prism_f2_sc_256", (20.0, 20.0, 20.0), 256, 2.0, 80e3, 0.020, 2,
+             (16, 16), (SC1,), seed=0, structure="sc"),
+    Workload("multislice_np_1024", (100.0, 100.0, 100.0), 1024, 2.0, 200e3, 0.020, 0,
+             (64, 64), (AU, C), seed=1, structure="np"),
+    Workload("prism_f4_np_1024", (100.0, 100.0, 100.0), 1024, 2.0, 200e3, 0.020, 4,
+             (128, 128), (AU, C), seed=2, structure="np"),
+    Workload("prism_f8_np_2048", (200.0, 200.0, 100.0), 2048, 2.0, 200e3, 0.020, 8,
+             (256, 256), (AU, C), seed=3, structure="np"),
+)}
 
 
 # ---------------------------------------------------------------------------
@@ -200,7 +201,7 @@ def serving_stream(n_requests: int, rate: float, seed: int = 4, grids=(256, 512,
 
 def serving_sample(cell, seed: int):
     """Callable giving the specimen of a serving request: the nanoparticle in
-    an amorphous matrix of config 1, scaled to `cell`, seeded with `seed`."""
+    an amorphous matrix of the 1024^2 workloads, scaled to `cell`, seeded with `seed`."""
     def make():
         pos, sp = nanoparticle_in_amorphous(cell, rng=np.random.default_rng(seed))
         return pos, sp, (AU, C)
