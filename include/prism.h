@@ -174,7 +174,9 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S,
  * previous one, so that row and column passes of different beams run
  * together.  The call still returns with all work ordered on `stream`, and
  * the S-matrix is identical to the one-stream build (n = 1).  Batches of
- * fewer than n beams use as many streams as beams.
+ * fewer than n beams use as many streams as beams.  At most 32 caller
+ * streams get partners; builds on any further caller stream run on that
+ * stream alone.
  * Errors: PRISM_E_INVAL (n outside 1..4). */
 int prism_set_build_streams(int32_t n);
 

@@ -524,9 +524,15 @@ std::atomic<int> g_build_streams{2};
 std::mutex g_partner_mu;
 std::map<hipStream_t, std::vector<hipStream_t>> g_partner;
 
-// The first `count` partner streams of st, created on first use.
-int partner_streams(hipStream_t st, int count, hipStream_t* out) {
+// The first `count` partner streams of st, created on first use.  At most
+// kMaxPartnered caller streams get partners (the library never destroys a
+// stream that may still hold work); *out_count is 0 for any further caller
+// stream, whose builds then run on that stream alone.
+constexpr size_t kMaxPartnered = 32;
+int partner_streams(hipStream_t st, int count, hipStream_t* out, int* out_count) {
     std::lock_guard<std::mutex> lk(g_partner_mu);
+    *out_count = 0;
+    if (g_partner.find(st) == g_partner.end() && g_partner.size() >= kMaxPartnered) return PRISM_OK;
     std::vector<hipStream_t>& v = g_partner[st];
     while ((int)v.size() < count) {
         hipStream_t p = nullptr;
@@ -534,6 +540,7 @@ int partner_streams(hipStream_t st, int count, hipStream_t* out) {
         v.push_back(p);
     }
     for (int i = 0; i < count; ++i) out[i] = v[i];
+    *out_count = count;
     return PRISM_OK;
 }
 
@@ -596,7 +603,14 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
         HIP_TRY(timed(PRISM_K_FINAL, q, [&] { return launch_smatrix_final(n, Wq, Sq, pd.tw_half, cnt, q); }));
         return PRISM_OK;
     };
-    const int P = std::min(g_build_streams.load(), NB);
+    int P = std::min(g_build_streams.load(), NB);
+    hipStream_t q[kMaxBuildStreams] = {st};
+    if (P > 1) {
+        int got = 0;
+        rc = partner_streams(st, P - 1, q + 1, &got);
+        if (rc) return rc;
+        if (got < P - 1) P = 1;
+    }
     if (P <= 1) {
         for (int b0 = 0; b0 < B; b0 += NB) {
             rc = run_items(b0, 0, std::min(NB, B - b0), st, nullptr);
@@ -609,9 +623,6 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     // batch leaves the tail parts empty), so no two streams ever touch the
     // same item; the forks of the first batch and the final joins are the
     // only cross-stream orderings needed.
-    hipStream_t q[kMaxBuildStreams] = {st};
-    rc = partner_streams(st, P - 1, q + 1);
-    if (rc) return rc;
     BuildEvents be;
     for (int k = 0; k < 2 * P; ++k) HIP_TRY(hipEventCreateWithFlags(&be.ev[k], hipEventDisableTiming));
     auto off = [&](int k) { return (int)((int64_t)k * NB / P); };
