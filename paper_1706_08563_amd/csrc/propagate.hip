@@ -52,6 +52,52 @@ constexpr int WG = 256;      // 4 wavefronts
 #define PRISM_PASSB_COLS 8       // adjacent columns per transform group in pass B (pipelined loads)
 #endif
 
+// Non-temporal wave-buffer traffic, measured at n = 1024 (1245 beams): in the
+// column pass it takes 2.08 -> 1.95 ms per launch; in the row pass it costs
+// 3.23 -> 3.58 ms (the column pass then misses the copy it would find in the
+// last-level cache), so it stays off there.
+#ifndef PRISM_NT_A
+#define PRISM_NT_A 0             // 1: row-pass wave-buffer loads and stores non-temporal
+#endif
+#ifndef PRISM_NT_BL
+#define PRISM_NT_BL 1            // 1: column-pass wave-buffer loads non-temporal
+#endif
+#ifndef PRISM_NT_BS
+#define PRISM_NT_BS 1            // 1: column-pass wave-buffer stores non-temporal
+#endif
+// Wave-buffer traffic: each element is read and written once per pass, with
+// no reuse within the pass.
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ float2 wave_load(const float2* p) {
+    if constexpr (NT) {
+        const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+        return make_float2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ float4 wave_load(const float4* p) {
+    if constexpr (NT) {
+        const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void wave_store(float2* p, float2 v) {
+    if constexpr (NT) __builtin_nontemporal_store(nt_f2{v.x, v.y}, reinterpret_cast<nt_f2*>(p));
+    else *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void wave_store(float4* p, float4 v) {
+    if constexpr (NT) __builtin_nontemporal_store(nt_f4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_f4*>(p));
+    else *p = v;
+}
+
 // Columns per pass-B transform group: pipelined when the column count allows.
 template <int N, int MODE>
 struct PassBCols {
@@ -149,7 +195,7 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
         // all loads of the tile in flight before the first LDS store
         float2 ld[NLD];
 #pragma unroll
-        for (int k = 0; k < NLD; ++k) ld[k] = gW[(size_t)k * JS * CS];
+        for (int k = 0; k < NLD; ++k) ld[k] = wave_load<PRISM_NT_A>(gW + (size_t)k * JS * CS);
 #pragma unroll
         for (int k = 0; k < NLD; ++k) lds_slot(k) = ld[k];
         __syncthreads();
@@ -226,7 +272,7 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) gW[(size_t)k * JS * CS] = lds_slot(k);
+    for (int k = 0; k < NLD; ++k) wave_store<PRISM_NT_A>(gW + (size_t)k * JS * CS, lds_slot(k));
 }
 
 // Waves per SIMD asked of the register allocator: two for the two-wavefront
@@ -340,7 +386,7 @@ __device__ __forceinline__ void pass_b_block(float2* __restrict__ W, const PropT
             F::template run<+1>(o, lds, tw, lt);
         }
 #pragma unroll
-        for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
+        for (int i = 0; i < E; ++i) wave_store<PRISM_NT_BS>(col4 + lt + LPT * i, make_float4(e[i].x, e[i].y, o[i].x, o[i].y));
         return;
     } else {
         // software pipeline over NC columns: the next column's loads are in
@@ -359,7 +405,7 @@ __device__ __forceinline__ void pass_b_block(float2* __restrict__ W, const PropT
         for (int d = 0; d < DEPTH && d < NC; ++d) {
             const float4* c4 = reinterpret_cast<const float4*>(Wi + (size_t)(j0 + d) * wave_col_stride(N));
 #pragma unroll
-            for (int i = 0; i < E; ++i) ring[d][i] = c4[lt + LPT * i];
+            for (int i = 0; i < E; ++i) ring[d][i] = wave_load<PRISM_NT_BL>(c4 + lt + LPT * i);
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -369,7 +415,7 @@ __device__ __forceinline__ void pass_b_block(float2* __restrict__ W, const PropT
             if (c + DEPTH < NC) {
                 const float4* n4 = reinterpret_cast<const float4*>(col + DEPTH * wave_col_stride(N));
 #pragma unroll
-                for (int i = 0; i < E; ++i) ring[(c + DEPTH) % (DEPTH + 1)][i] = n4[lt + LPT * i];
+                for (int i = 0; i < E; ++i) ring[(c + DEPTH) % (DEPTH + 1)][i] = wave_load<PRISM_NT_BL>(n4 + lt + LPT * i);
             }
 #pragma unroll
             for (int i = 0; i < E; ++i) {
@@ -412,7 +458,7 @@ __device__ __forceinline__ void pass_b_block(float2* __restrict__ W, const PropT
                     F::template run<+1>(o, lds, tw, lt);
                 }
 #pragma unroll
-                for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
+                for (int i = 0; i < E; ++i) wave_store<PRISM_NT_BS>(col4 + lt + LPT * i, make_float4(e[i].x, e[i].y, o[i].x, o[i].y));
             }
         }
     }
@@ -465,7 +511,7 @@ __global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, Prop
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
             const int idx = tid + k * WG, c = idx / L, m = idx % L;
-            ld[k] = reinterpret_cast<const float4*>(Wi + (size_t)(jb + c) * wave_col_stride(N))[m];
+            ld[k] = wave_load<PRISM_NT_BL>(reinterpret_cast<const float4*>(Wi + (size_t)(jb + c) * wave_col_stride(N)) + m);
         }
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
@@ -511,7 +557,7 @@ __global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, Prop
         F::template run<+1>(o, xo, tw, lt);
         float4* col4 = reinterpret_cast<float4*>(Wi + (size_t)j * wave_col_stride(N));
 #pragma unroll
-        for (int i = 0; i < E; ++i) col4[lt + LPT * i] = make_float4(e[i].x, e[i].y, o[i].x, o[i].y);
+        for (int i = 0; i < E; ++i) wave_store<PRISM_NT_BS>(col4 + lt + LPT * i, make_float4(e[i].x, e[i].y, o[i].x, o[i].y));
     }
 }
 
