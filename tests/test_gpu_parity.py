@@ -419,3 +419,23 @@ def test_device_copy(P):
     P.prism_device_copy(x, y)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+# ------------------------------------------------ stored oracle fixture --
+def test_gpu_matches_stored_oracle_fixture(P):
+    """The 64^2 fixture written by tests/golden/make_golden.py (oracle only)."""
+    from test_oracle_pins import read_tiny_prism_fixture
+    say("stored oracle fixture 64^2: prism f=2 (fp32, split-bf16) and multislice")
+    xy, prism_ref, ms_ref = read_tiny_prism_fixture()
+    w, pos, sp = W.small_workload(n=64, cell=(10.0, 10.0, 4.0), n_atoms=8, f=2, seed=11)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    S = P.prism_build_smatrix(d, V)
+    plan = P.prism_probe_plan_upload(d, xy)
+    for name, prec in (("fp32", P.PRISM_FP32), ("bf16x3", P.PRISM_SPLIT_BF16X3)):
+        out = P.prism_probe_outputs(d, S, plan, prec)
+        _sync()
+        _check_D(out.cpu().numpy().astype(np.float64), prism_ref, f"fixture prism {name}")
+    ms = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=3)
+    _sync()
+    _check_D(ms.cpu().numpy().astype(np.float64), ms_ref, "fixture multislice")

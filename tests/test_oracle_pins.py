@@ -6,6 +6,7 @@ exactness of PRISM at f = 1 (the plane-wave basis is then complete, "Description
 of Algorithms").  None of these compares the oracle with the GPU path.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -45,11 +46,15 @@ def test_fourier_indices_order():
 # table of electron wavelength and sigma vs. accelerating voltage), and the
 # independent closed form sigma = 2 pi/(lambda E0) (m0 c^2 + e E0)/(2 m0 c^2 + e E0).
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("E0,lam,sig", [
-    (100e3, 0.03701, 0.00092440),
-    (200e3, 0.02508, 0.00072884),
-    (300e3, 0.01969, 0.00065262),
-])
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden_table(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return [tuple(float(x) for x in line.split()) for line in fh if line.strip() and not line.startswith("#")]
+
+
+@pytest.mark.parametrize("E0,lam,sig", _golden_table("electron_wavelength_sigma.txt"))
 def test_wavelength_and_sigma_textbook(E0, lam, sig):
     assert abs(O.wavelength(E0) - lam) / lam < 2e-4
     assert abs(O.interaction_constant(E0) - sig) / sig < 2e-4
@@ -497,3 +502,34 @@ def test_frozen_phonon_average_of_identical_configs_is_single_run():
     singles = [O.frozen_phonon_prism([c], sp, w.species, w.cell, w.dz, w.n, w.E0, w.alpha_max, 2, xy) for c in cfgs]
     assert O.rel_err(two, 0.5 * (singles[0] + singles[1])) < 1e-14
     assert O.rel_err(singles[0], singles[1]) > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Regression fixture: the oracle's 3D outputs on a 64^2 random cell as written
+# by tests/golden/make_golden.py (oracle only).  Guards the oracle against
+# unintended changes; any intended change to its arithmetic regenerates the
+# fixture in the same commit.
+# ---------------------------------------------------------------------------
+def read_tiny_prism_fixture():
+    probes, prism, ms = [], [], []
+    with open(os.path.join(GOLDEN, "tiny_prism_f2_64.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            tag, *vals = line.split()
+            v = [float(x) for x in vals]
+            {"probe": probes, "prism": prism, "multislice": ms}[tag].append(v)
+    return np.array(probes), np.array(prism), np.array(ms)
+
+
+def test_oracle_reproduces_tiny_prism_fixture():
+    xy, prism_ref, ms_ref = read_tiny_prism_fixture()
+    w, pos, sp = W.small_workload(n=64, cell=(10.0, 10.0, 4.0), n_atoms=8, f=2, seed=11)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    V = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    beams = O.beam_set(w.n, w.cell[0], lam, w.alpha_max, w.f)
+    S = O.build_smatrix(V, w.cell[0], w.dz, lam, sig, beams)
+    prism = O.prism_outputs(S, beams, w.cell[0], w.n, lam, w.f, xy)
+    ms = O.multislice_outputs(V, w.cell[0], w.dz, lam, sig, w.alpha_max, xy)
+    assert np.allclose(prism, prism_ref, rtol=1e-12, atol=1e-15)
+    assert np.allclose(ms, ms_ref, rtol=1e-12, atol=1e-15)
