@@ -841,7 +841,7 @@ int prism_probe_diffraction(const prism_smatrix_desc* d, const void* S, const pr
     size_t need = 0;
     int rc = synth_validate(&jb, 1, precision, &need);
     if (rc) return rc;
-    if (!out4d) return fail(PRISM_E_INVAL, "probe diffraction: NULL output");
+    if (!out4d && plan->n_probes > 0) return fail(PRISM_E_INVAL, "probe diffraction: NULL output");
     if (!ws || ws_bytes < plan->ws_bytes)
         return fail(PRISM_E_WORKSPACE, "probe diffraction: workspace %zu < %zu bytes", ws_bytes, plan->ws_bytes);
     if (plan->n_probes == 0) return PRISM_OK;
@@ -1035,7 +1035,8 @@ static int multislice_run(const prism_grid* grid, double E0, double alpha_max, c
     int rc = check_grid(grid);
     if (rc) return rc;
     const bool streaming = V_host != nullptr;
-    if ((!V && !V_host) || !out || (n_probes > 0 && !probe_xy) || n_probes < 0 || batch < 1 || !(E0 > 0) ||
+    if ((!V && !V_host) || (!out && n_probes > 0) || (n_probes > 0 && !probe_xy) || n_probes < 0 || batch < 1 ||
+        !(E0 > 0) ||
         !(alpha_max > 0) || !(dalpha > 0))
         return fail(PRISM_E_INVAL, "multislice: invalid argument");
     const int n = grid->n, Lh = n / 2, nsl = grid->n_slices;

@@ -439,3 +439,31 @@ def test_gpu_matches_stored_oracle_fixture(P):
     ms = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=3)
     _sync()
     _check_D(ms.cpu().numpy().astype(np.float64), ms_ref, "fixture multislice")
+
+
+# --------------------------------------------------------------- edge cases --
+def test_zero_probes_and_periodic_wrap(P):
+    """Empty probe lists give empty outputs on every synthesis entry point; a
+    probe shifted by whole cell periods gives the same outputs (to the FP64
+    rounding of the shifted phase arguments)."""
+    import torch
+    say("edge cases: zero probes; probe positions shifted by whole cells")
+    w, pos, sp = W.small_workload(n=64, n_atoms=12, seed=8, f=2)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    S = P.prism_build_smatrix(d, V)
+    none = np.zeros((0, 2))
+    plan0 = P.prism_probe_plan_upload(d, none)
+    assert tuple(P.prism_probe_outputs(d, S, plan0, P.PRISM_FP32).shape) == (0, plan0.plan.n_bins)
+    assert tuple(P.prism_probe_outputs(d, S, plan0, P.PRISM_SPLIT_BF16X3).shape) == (0, plan0.plan.n_bins)
+    assert P.prism_probe_diffraction(d, S, plan0, P.PRISM_FP32).shape[0] == 0
+    assert P.prism_probe_outputs_chunked(d, S, plan0, P.PRISM_SPLIT_BF16X3, beam_chunk=16).shape[0] == 0
+    assert P.multislice_outputs(g, w.E0, w.alpha_max, V, none, batch=4).shape[0] == 0
+    L = w.cell[0]
+    xy = np.array([[1.7, 3.1], [1.7 + L, 3.1 - 2 * L], [1.7 - 3 * L, 3.1 + L]])
+    out = P.prism_probe_outputs(d, S, P.prism_probe_plan_upload(d, xy), P.PRISM_FP32)
+    ms = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, batch=3)
+    torch.cuda.synchronize()
+    o, m = out.cpu().numpy(), ms.cpu().numpy()
+    for a in (o, m):
+        assert O.rel_err(a[1:2], a[0:1]) <= 1e-6 and O.rel_err(a[2:3], a[0:1]) <= 1e-6
