@@ -467,3 +467,26 @@ def test_zero_probes_and_periodic_wrap(P):
     o, m = out.cpu().numpy(), ms.cpu().numpy()
     for a in (o, m):
         assert O.rel_err(a[1:2], a[0:1]) <= 1e-6 and O.rel_err(a[2:3], a[0:1]) <= 1e-6
+
+
+def test_single_beam_aperture(P):
+    """An aperture so small that only the k = 0 beam is inside: one S-matrix
+    layer, a single partly filled K step of the contraction, one build stream."""
+    say("edge case: one-beam aperture")
+    w, pos, sp = W.small_workload(n=64, n_atoms=12, seed=9, f=2)
+    alpha = 1e-4
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, alpha, w.f)
+    assert d.n_beams == 1
+    S = P.prism_build_smatrix(d, V)
+    xy = np.array([[0.0, 0.0], [3.3, 8.1]])
+    plan = P.prism_probe_plan_upload(d, xy)
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    beams = O.beam_set(w.n, w.cell[0], lam, alpha, w.f)
+    ref = O.prism_outputs(O.build_smatrix(Vref, w.cell[0], w.dz, lam, sig, beams), beams, w.cell[0], w.n, lam,
+                          w.f, xy)
+    for prec in (P.PRISM_FP32, P.PRISM_SPLIT_BF16X3):
+        out = P.prism_probe_outputs(d, S, plan, prec)
+        _sync()
+        assert O.rel_err(out.cpu().numpy(), ref) <= TOL
