@@ -490,3 +490,26 @@ def test_single_beam_aperture(P):
         out = P.prism_probe_outputs(d, S, plan, prec)
         _sync()
         assert O.rel_err(out.cpu().numpy(), ref) <= TOL
+
+
+def test_window_corners_bit_exact(P):
+    """Index work: each probe's window corner in the uploaded plan equals the
+    oracle's nearest-pixel centre minus M/2 (periodic), including positions on
+    exact half-pixel ties, negative and beyond one cell."""
+    import torch
+    say("window corners vs oracle, ties and wrap")
+    w, pos, sp = W.small_workload(n=128, cell=(16.0, 16.0, 4.0), n_atoms=10, f=2, seed=4)
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    L, ns, M = w.cell[0], d.ns, d.m_win
+    step = 2.0 * L / w.n                               # S-grid pixel
+    rng = np.random.default_rng(17)
+    ties = (np.arange(-3, 70) + 0.5) * step
+    xy = np.concatenate([np.stack([ties, ties[::-1]], 1), rng.uniform(-2 * L, 3 * L, size=(200, 2))])
+    plan = P.prism_probe_plan_upload(d, xy)
+    torch.cuda.synchronize()
+    off = int(plan.plan.off[1])
+    raw = plan.dev[off:off + 8 * len(xy)].cpu().numpy().view(np.int32).reshape(-1, 2)
+    ref = np.array([[(O.window_centre(x, L, w.n) - M // 2) % ns, (O.window_centre(y, L, w.n) - M // 2) % ns]
+                    for x, y in xy], dtype=np.int32)
+    assert np.array_equal(raw, ref)
