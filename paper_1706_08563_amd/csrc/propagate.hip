@@ -16,7 +16,9 @@
 //   psi(2m)   = IDFT_{n/2}[Phi_j](m)
 //   psi(2m+1) = IDFT_{n/2}[Phi_j e^{+2 pi i kx(j)/n}](m)
 //   Phi_j     = DFT_{n/2}[psi(2m)]_j + e^{-2 pi i kx(j)/n} DFT_{n/2}[psi(2m+1)]_j
-// so all transforms here have length n/2 and live in one wavefront.
+// so all transforms here have length n/2: one wavefront per transform, or
+// two for the 1024-point transforms of the row and tiled column passes at
+// n = 2048 (see FftFor below).
 #include "fft.hpp"
 #include "kernels.hpp"
 
@@ -472,12 +474,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
     pass_b_block<N, MODE>(W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, blockIdx.x, smem);
 }
 
-// Tile-staged column pass for interior slices (one transform per wavefront,
-// n >= 1024): a workgroup stages TC whole columns into LDS with all its loads
-// in flight at once (as pass A stages its row tile), then each wavefront
-// transforms its columns from LDS, using each column's own LDS slots as the
-// two padded exchange buffers of its even and odd transforms, and writes the
-// result straight from registers.
+// Tile-staged column pass for interior slices (used from n = 2048, one
+// transform per wavefront pair there): a workgroup stages TC whole columns
+// into LDS with all its loads in flight at once (as pass A stages its row
+// tile), then the wavefronts transform the columns from LDS, using each
+// column's own LDS slots as the two padded exchange buffers of its even and
+// odd transforms, and write the result straight from registers.
 #ifndef PRISM_PASSB_TILE_MIN
 #define PRISM_PASSB_TILE_MIN 2048   // smallest n whose interior column passes use k_pass_b_tile
 #endif
