@@ -353,6 +353,16 @@ int multislice_outputs_streaming(const prism_grid* grid, double E0, double alpha
 int prism_detector_bin_map(double lambda, double Lw, double alpha_aa, double dalpha,
                            int32_t n_bins, int32_t m, int32_t* map);
 
+/* Detector extent of a grid ("Multislice Probe Simulations", Fig. 1e: annular
+ * bins up to the largest angle the band-limited propagation of Eq. 2 keeps):
+ * alpha_aa = lambda n / (4 L), the anti-aliasing angle, and
+ * n_bins = ceil(alpha_aa / dalpha), the bin count that multislice_outputs and
+ * prism_probe_plan_init use when given n_bins <= 0.  `alpha_aa` may be NULL.
+ * Host only.  Errors: PRISM_E_INVAL (E0 <= 0, dalpha <= 0, NULL n_bins or grid),
+ * those of prism_grid_init for the grid. */
+int prism_detector_default_bins(const prism_grid* grid, double E0, double dalpha, int32_t* n_bins,
+                                double* alpha_aa);
+
 /* ---- kernel timing (diagnostics) --------------------------------------------- */
 
 #define PRISM_K_PASS_A         0   /* row pass: inverse row DFT, transmission, forward row DFT */

@@ -31,7 +31,7 @@ from .stem import (  # noqa: F401
     alpha_aa, default_n_bins, bin_map,
     beam_set, probe_coefficients, aberration_phase,
     multislice_outputs, multislice_exit_spectrum,
-    smatrix_layer, build_smatrix,
+    smatrix_layer, build_smatrix, smatrix_windows, prism_outputs_streamed,
     window_centre, probe_window, prism_outputs, prism_diffraction, frozen_phonon_prism,
     rel_err, adf_signal,
 )

@@ -31,6 +31,7 @@ leaves open:
 from __future__ import annotations
 
 import math
+import multiprocessing
 
 import numpy as np
 import scipy.fft as sfft
@@ -263,18 +264,23 @@ def multislice_exit_spectrum(V, L: float, dz: float, lam: float, sigma: float,
 
 def multislice_outputs(V, L: float, dz: float, lam: float, sigma: float, alpha_max: float,
                        probe_xy, dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0,
-                       C3: float = 0.0):
-    """D[p][bin] = sum over bin of |Psi_exit|^2 / n^4 for each probe (3D output)."""
+                       C3: float = 0.0, processes: int = 1):
+    """D[p][bin] = sum over bin of |Psi_exit|^2 / n^4 for each probe (3D output).
+
+    Probes are independent; `processes` > 1 runs them in forked worker
+    processes (same arithmetic per probe)."""
     S, n, _ = V.shape
     if n_bins is None:
         n_bins = default_n_bins(lam, n, L, dalpha)
     bmap = bin_map(lam, n, L, alpha_aa(lam, n, L), dalpha, n_bins)
     probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
-    D = np.zeros((len(probe_xy), n_bins))
-    for p in range(len(probe_xy)):
+
+    def one(p):
         Psi = multislice_exit_spectrum(V, L, dz, lam, sigma, alpha_max, probe_xy[p], C1, C3)
-        D[p] = detect(np.abs(Psi) ** 2 / float(n) ** 4, bmap, n_bins)
-    return D
+        return detect(np.abs(Psi) ** 2 / float(n) ** 4, bmap, n_bins)
+
+    rows = _fork_map(one, range(len(probe_xy)), processes)
+    return np.array(rows, dtype=np.float64).reshape(len(probe_xy), n_bins)
 
 
 # ---------------------------------------------------------------------------
@@ -374,6 +380,84 @@ def frozen_phonon_prism(configs, species_idx, species, cell, dz: float, n: int, 
         D = prism_outputs(build_smatrix(V, L, dz, lam, sig, beams), beams, L, n, lam, f, probe_xy, C1=C1, C3=C3)
         acc = D if acc is None else acc + D
     return acc / len(configs)
+
+
+# ---------------------------------------------------------------------------
+# PRISM without storing the S-matrix.  The paper's streaming memory model
+# ("Streaming Data for Very Large Simulations") keeps only the data of the
+# current step on the device; applied here, each beam's layer is built, its
+# contribution c_b(p) S_b is added into every probe's window, and the layer is
+# dropped.  The window sum is linear in the beams, so the result equals
+# build_smatrix followed by prism_outputs (up to the order of the FP64 sums)
+# while holding P windows instead of |B| layers.
+# ---------------------------------------------------------------------------
+def smatrix_windows(t, P, beams, coeffs, centres, M: int):
+    """sum over the given beams of coeffs[p][b] times beam b's layer cropped to
+    probe p's window: [len(centres)][M][M] complex128."""
+    acc = np.zeros((len(centres), M, M), dtype=np.complex128)
+    for b, (kx, ky) in enumerate(beams):
+        layer = smatrix_layer(t, P, int(kx), int(ky))[None]
+        for p, (cx, cy) in enumerate(centres):
+            acc[p] += probe_window(layer, coeffs[p, b:b + 1], cx, cy, M)
+    return acc
+
+
+def prism_outputs_streamed(V, L: float, dz: float, lam: float, sigma: float, beams, n: int, f: int, probe_xy,
+                           dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0, C3: float = 0.0,
+                           processes: int = 1, groups: int | None = None):
+    """D[p][bin] of prism_outputs(build_smatrix(V, ...), ...) with the beams
+    streamed through window accumulators; `groups` beam groups are summed in
+    `processes` forked worker processes."""
+    Ns = n // 2
+    M = Ns // f
+    Lw = L / f
+    if n_bins is None:
+        n_bins = default_n_bins(lam, n, L, dalpha)
+    bmap = bin_map(lam, M, Lw, alpha_aa(lam, n, L), dalpha, n_bins)
+    probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
+    t = transmission(V, sigma)
+    P = propagator(n, L, lam, dz)
+    C = probe_coefficients(beams, L, probe_xy, lam, C1, C3)
+    centres = [(window_centre(x, L, n), window_centre(y, L, n)) for x, y in probe_xy]
+    parts = np.array_split(np.arange(len(beams)), max(1, groups or processes))
+
+    def one(idx):
+        return smatrix_windows(t, P, beams[idx], C[:, idx], centres, M)
+
+    w = np.zeros((len(probe_xy), M, M), dtype=np.complex128)
+    for part in _fork_map(one, parts, processes):
+        w += part
+    D = np.zeros((len(probe_xy), n_bins))
+    for p in range(len(probe_xy)):
+        D[p] = detect(np.abs(fft2(w[p])) ** 2 / float(M) ** 4, bmap, n_bins)
+    return D
+
+
+# ---------------------------------------------------------------------------
+# Worker processes for the independent items above (probes of multislice,
+# beam groups of the streamed PRISM).  Forked children inherit the inputs;
+# each runs its transforms on one thread.
+# ---------------------------------------------------------------------------
+_FORK_TASK = None
+
+
+def _fork_call(i):
+    global WORKERS
+    WORKERS = 1
+    return _FORK_TASK(i)
+
+
+def _fork_map(fn, items, processes: int):
+    global _FORK_TASK
+    items = list(items)
+    if processes <= 1 or len(items) <= 1:
+        return [fn(x) for x in items]
+    _FORK_TASK = lambda i: fn(items[i])  # noqa: E731
+    try:
+        with multiprocessing.get_context("fork").Pool(min(processes, len(items))) as pool:
+            return pool.map(_fork_call, range(len(items)), chunksize=1)
+    finally:
+        _FORK_TASK = None
 
 
 # ---------------------------------------------------------------------------

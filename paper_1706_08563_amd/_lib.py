@@ -106,6 +106,8 @@ _SIGNATURES = {
                                       c_void_p, c_int64, c_double, c_int32, c_int32, c_void_p, c_void_p, c_size_t,
                                       c_void_p, c_void_p], c_int32),
     "prism_detector_bin_map": ([c_double, c_double, c_double, c_double, c_int32, c_int32, c_void_p], c_int32),
+    "prism_detector_default_bins": ([POINTER(prism_grid), c_double, c_double, POINTER(c_int32), POINTER(c_double)],
+                                    c_int32),
     "prism_set_build_streams": ([c_int32], c_int32),
     "prism_device_copy": ([c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "prism_timing_enable": ([c_int32], c_int32),

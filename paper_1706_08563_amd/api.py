@@ -69,6 +69,15 @@ def prism_detector_bin_map(lam: float, Lw: float, alpha_aa: float, dalpha: float
 
 
 # ------------------------------------------------------------ potential --
+def prism_detector_default_bins(grid: prism_grid, E0: float, dalpha: float = 1e-3):
+    """(n_bins, alpha_aa): the default detector extent of a grid."""
+    nb = ctypes.c_int32()
+    a = ctypes.c_double()
+    check(lib.prism_detector_default_bins(ctypes.byref(grid), float(E0), float(dalpha), ctypes.byref(nb),
+                                          ctypes.byref(a)))
+    return nb.value, a.value
+
+
 def prism_project_potential(pos, species_idx, species, grid: prism_grid, device=None):
     """V [n_slices, n, n] float32 on the device from host atoms."""
     torch = _torch()
@@ -211,9 +220,7 @@ def multislice_outputs(grid: prism_grid, E0: float, alpha_max: float, V, xy, dal
     torch = _torch()
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
     if n_bins <= 0:
-        # alpha_AA depends on the grid only; any legal interpolation factor reports it
-        f = max(1, (grid.n // 2) // 128)
-        n_bins = int(np.ceil(prism_smatrix_plan(grid, E0, alpha_max, f).alpha_aa / dalpha))
+        n_bins = prism_detector_default_bins(grid, E0, dalpha)[0]
     if ws is None:
         ws = _workspace(multislice_workspace(grid, batch, len(xy)), V.device)
     if out is None:
@@ -321,8 +328,7 @@ def multislice_outputs_streaming(grid: prism_grid, E0: float, alpha_max: float, 
     assert V_host.device.type == "cpu" and V_host.dtype == torch.float32 and V_host.is_contiguous()
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
     if n_bins <= 0:
-        f = max(1, (grid.n // 2) // 128)
-        n_bins = int(np.ceil(prism_smatrix_plan(grid, E0, alpha_max, f).alpha_aa / dalpha))
+        n_bins = prism_detector_default_bins(grid, E0, dalpha)[0]
     if ws is None:
         ws = _workspace(multislice_streaming_workspace(grid, batch, len(xy)))
     if out is None:

@@ -388,6 +388,17 @@ int prism_detector_bin_map(double lambda, double Lw, double alpha_aa, double dal
     return PRISM_OK;
 }
 
+int prism_detector_default_bins(const prism_grid* grid, double E0, double dalpha, int32_t* n_bins,
+                                double* alpha_aa) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    if (!n_bins || !(E0 > 0) || !(dalpha > 0)) return fail(PRISM_E_INVAL, "default bins: invalid argument");
+    const double a = alpha_aa_of(wavelength_A(E0), grid->n, grid->cell[0]);
+    *n_bins = default_bins(a, dalpha);
+    if (alpha_aa) *alpha_aa = a;
+    return PRISM_OK;
+}
+
 // ------------------------------------------------------------ potential --
 int prism_project_potential_workspace(int64_t n_atoms, size_t* bytes) {
     if (!bytes || n_atoms < 0) return fail(PRISM_E_INVAL, "invalid argument");

@@ -103,6 +103,26 @@ def test_bin_map_edges_and_explicit_bin_count():
                               O.bin_map(lam, m, Lw, a_aa, 1e-3, nb))
 
 
+@pytest.mark.parametrize("cfg", ["prism_f2_sc_256", "multislice_np_1024", "prism_f8_np_2048"])
+@pytest.mark.parametrize("dalpha", [1e-3, 2.5e-3, 0.7e-3])
+def test_detector_default_bins_query_matches_oracle(cfg, dalpha):
+    """The library reports the default detector extent (the binding computes
+    none of it): alpha_AA and ceil(alpha_AA / dalpha) equal the oracle's."""
+    P = _lib()
+    w = W.WORKLOADS[cfg]
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    lam = O.wavelength(w.E0)
+    nb, a = P.prism_detector_default_bins(g, w.E0, dalpha)
+    assert a == O.alpha_aa(lam, w.n, w.cell[0])
+    assert nb == O.default_n_bins(lam, w.n, w.cell[0], dalpha)
+    if dalpha == 1e-3:
+        assert nb == (134 if w.n == 256 else 65)
+    for bad in ((0.0, dalpha), (w.E0, 0.0), (w.E0, -1e-3)):
+        with pytest.raises(P.PrismError) as e:
+            P.prism_detector_default_bins(g, *bad)
+        assert e.value.code == P.PRISM_E_INVAL
+
+
 def test_probe_plan_sizes():
     P = _lib()
     w = W.WORKLOADS["prism_f2_sc_256"]

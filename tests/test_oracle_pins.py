@@ -533,3 +533,92 @@ def test_oracle_reproduces_tiny_prism_fixture():
     ms = O.multislice_outputs(V, w.cell[0], w.dz, lam, sig, w.alpha_max, xy)
     assert np.allclose(prism, prism_ref, rtol=1e-12, atol=1e-15)
     assert np.allclose(ms, ms_ref, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Error metrics and the detector's extent, each against values fixed by hand.
+# ---------------------------------------------------------------------------
+def test_rel_err_known_pair():
+    # difference (0, 0, 0, -4) has norm 4; the reference (1, 2, 2, 4) has norm 5
+    D = np.array([[1.0, 2.0], [2.0, 0.0]])
+    Dref = np.array([[1.0, 2.0], [2.0, 4.0]])
+    assert O.rel_err(D, Dref) == 0.8
+    assert O.rel_err(Dref, Dref) == 0.0
+    # relative to the second argument, not the first
+    assert O.rel_err(Dref, D) == 4.0 / 3.0
+
+
+def test_adf_signal_bins_at_the_inner_angle():
+    # bin b holds 2^b: the dark-field sum from 40 mrad counts bins 40..64
+    # only, i.e. 2^65 - 2^40 (bin 39 = [39, 40) mrad is bright field; bins
+    # 40 and 41 are in), both exact in binary
+    D = np.array([2.0 ** np.arange(65), np.zeros(65)])
+    D[1, 39], D[1, 40], D[1, 41] = 1.0, 10.0, 100.0
+    adf = O.adf_signal(D, 1e-3, 0.04)
+    assert adf[0] == 2.0 ** 65 - 2.0 ** 40
+    assert adf[1] == 110.0
+    # the inner angle is a bin edge whatever its rounding in binary
+    assert O.adf_signal(D, 1e-3, 0.041)[1] == 100.0
+    assert O.adf_signal(D, 1e-3, 0.039)[1] == 111.0
+
+
+@pytest.mark.parametrize("E0,n,L,n_bins", [(80e3, 256, 20.0, 134), (200e3, 1024, 100.0, 65),
+                                           (200e3, 2048, 200.0, 65)])
+def test_antialias_angle_is_the_propagator_band_edge(E0, n, L, n_bins):
+    """alpha_AA is the scattering angle where the propagator's band limit cuts
+    off: a Fourier pixel passes the band-limit mask exactly when its angle
+    lam |k| / L is below alpha_AA (checked on every pixel of the grid), and the
+    default bin count is the least number of 1 mrad bins that covers every
+    pixel inside the band (the values of the benchmark geometries: 134 at
+    80 keV, 20 A, 256^2; 65 at 200 keV, 0.0977 A pixels)."""
+    lam = O.wavelength(E0)
+    a_aa = O.alpha_aa(lam, n, L)
+    k = O.fourier_indices(n)
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    ang = lam * np.sqrt((kx * kx + ky * ky).astype(np.float64)) / L
+    mask = O.band_limit_mask(n)
+    # the pixels with |k| = n/4 exactly lie on the edge (angle alpha_AA up to
+    # rounding) and are outside the band; every other pixel is clear of it,
+    # so there the comparison is exact
+    edge = 16 * (kx * kx + ky * ky) == n * n
+    assert edge.sum() == 4 and not mask[edge].any()
+    assert np.max(np.abs(ang[edge] - a_aa)) <= 4e-16 * a_aa
+    assert np.min(np.abs(ang[~edge] - a_aa)) > 1e-9 * a_aa
+    assert np.array_equal(mask[~edge], ang[~edge] < a_aa)
+    nb = O.default_n_bins(lam, n, L, 1e-3)
+    assert nb == n_bins
+    inside = ang[mask]
+    assert np.floor(inside.max() / 1e-3) == nb - 1
+
+
+# ---------------------------------------------------------------------------
+# PRISM with the beams streamed through window accumulators (no stored
+# S-matrix): the vacuum closed form, f = 1 against multislice, and the stored
+# form on a scattering cell, with the beams split over worker processes.
+# ---------------------------------------------------------------------------
+def test_prism_streamed_vacuum_closed_form():
+    n, L, E0, a, f = 64, 10.0, 80e3, 0.02, 2
+    lam, sig = O.wavelength(E0), O.interaction_constant(E0)
+    nb = O.default_n_bins(lam, n, L, 1e-3)
+    beams = O.beam_set(n, L, lam, a, f)
+    xy = np.array([[0.0, 0.0], [3.3, 7.1], [9.9, 0.2]])
+    D = O.prism_outputs_streamed(np.zeros((2, n, n)) + 5.0, L, 2.0, lam, sig, beams, n, f, xy, groups=3)
+    assert np.max(np.abs(D - _vacuum_expected(lam, n, L, a, f, 1e-3, nb)[None, :])) < 1e-13
+
+
+def test_prism_streamed_f1_equals_multislice_and_stored_form():
+    w, pos, sp = W.small_workload(n=64, n_atoms=16, seed=5)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    V = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    L = w.cell[0]
+    xy = np.array([[0.0, 0.0], [2.5, 7.5], [6.1, 3.9], [9.7, 9.7], [-1.2, 13.3]])
+    Dm = O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy)
+    Dm2 = O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy, processes=2)
+    assert np.array_equal(Dm, Dm2)
+    b1 = O.beam_set(w.n, L, lam, w.alpha_max, 1)
+    assert O.rel_err(O.prism_outputs_streamed(V, L, w.dz, lam, sig, b1, w.n, 1, xy, processes=2), Dm) < 1e-10
+    b2 = O.beam_set(w.n, L, lam, w.alpha_max, 2)
+    stored = O.prism_outputs(O.build_smatrix(V, L, w.dz, lam, sig, b2), b2, L, w.n, lam, 2, xy)
+    streamed = O.prism_outputs_streamed(V, L, w.dz, lam, sig, b2, w.n, 2, xy, processes=2, groups=5)
+    assert O.rel_err(streamed, stored) < 1e-13
+    assert O.rel_err(stored, Dm) > 1e-4      # f = 2 differs from multislice: the check is not vacuous

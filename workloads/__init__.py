@@ -68,7 +68,7 @@ WORKLOADS = {w.name: w for w in (
     Workload("multislice_np_1024", (100.0, 100.0, 100.0), 1024, 2.0, 200e3, 0.020, 0,
              (64, 64), (AU, C), seed=1, structure="np"),
     Workload("prism_f4_np_1024", (100.0, 100.0, 100.0), 1024, 2.0, 200e3, 0.020, 4,
-             (128, 128), (AU, C), seed=2, structure="np"),
+             (128, 128), (AU, C), seed=1, structure="np"),
     Workload("prism_f8_np_2048", (200.0, 200.0, 100.0), 2048, 2.0, 200e3, 0.020, 8,
              (256, 256), (AU, C), seed=3, structure="np"),
 )}
