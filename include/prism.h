@@ -226,9 +226,11 @@ typedef struct prism_probe_job {
     const void* plan_dev;             /* device plan tables */
     float* out;                       /* device float32 [n_probes][n_bins] (3D output), or NULL */
     float* diffraction;               /* device float32 [n_probes][m_win][m_win] (4D output), or NULL */
-    float out_scale;                  /* out = out_scale * bin sums ...                    */
-    int32_t accumulate;               /* ... + the previous contents of out when 1 (e.g.
-                                         averaging frozen-phonon configurations); 0 or 1 */
+    float out_scale;                  /* out = out_scale * bin sums, diffraction =
+                                         out_scale * intensities ...                       */
+    int32_t accumulate;               /* ... + the previous contents of out (and of
+                                         diffraction) when 1, e.g. averaging frozen-phonon
+                                         configurations of the 3D or 4D output; 0 or 1 */
 } prism_probe_job;
 
 /* Workspace bytes of prism_probe_outputs_batched for these jobs. */

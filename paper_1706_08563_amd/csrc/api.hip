@@ -721,7 +721,9 @@ int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
     int maxpt = 0;
     rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, plan->C1, plan->C3, h, maxpt);
     if (rc) return rc;
-    if ((int64_t)h.tile_probes.size() != plan->n_entries || (int)h.perm.size() != plan->n_binned)
+    // every size the kernels and the workspace depend on must be the plan's
+    if ((int64_t)h.tile_probes.size() != plan->n_entries || (int)h.perm.size() != plan->n_binned ||
+        maxpt != plan->max_per_tile || (int64_t)h.tile_start.size() - 1 != plan->n_tiles)
         return fail(PRISM_E_INVAL, "probe plan upload: plan does not match these probes");
     std::vector<char> blob(plan->plan_bytes, 0);
     auto put = [&](size_t off, const void* src, size_t bytes) {
@@ -788,7 +790,12 @@ static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, voi
         }
         void* ss = split_s_carve(jobs[k].desc, c);
         s_op[k] = split ? ss : jobs[k].S;
-        if (split && jobs[k].plan->n_probes > 0) {
+        // the split copy serves every job on this S-matrix: convert it when
+        // any of them has probes (the first may have none)
+        bool used = false;
+        for (int i = k; i < n_jobs && !used; ++i)
+            used = jobs[i].plan->n_probes > 0 && first_with_same_s(jobs, i) == k;
+        if (split && used) {
             const prism_smatrix_desc* d = jobs[k].desc;
             HIP_TRY(timed(PRISM_K_SPLIT, st, [&] {
                 return launch_split_s(precision, static_cast<const float2*>(jobs[k].S), ss, d->n_beams, d->ns, st);

@@ -597,8 +597,12 @@ __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
     }
     __syncthreads();
     if (diff) {
+        // the 4D output takes the same scale and accumulation as the 3D one
         float* d = diff + (size_t)p * M * M;
-        for (int idx = tid; idx < M * M; idx += WG) d[idx] = buf[(idx / M) * ROW + idx % M].x;
+        for (int idx = tid; idx < M * M; idx += WG) {
+            const float v = job.scale * buf[(idx / M) * ROW + idx % M].x;
+            d[idx] = job.accumulate ? d[idx] + v : v;
+        }
     }
     if (!out) return;
     for (int b = wave; b < n_bins; b += 4) {
@@ -702,11 +706,22 @@ __global__ __launch_bounds__(WG) void k_window_cols(const float2* __restrict__ w
     }
 }
 
+// diff = scale * inten (+ diff when accumulating): the 4D output of a large
+// window when it is scaled or accumulated (the bins read the plain intensity).
+__global__ __launch_bounds__(WG) void k_scale_into(float* __restrict__ diff, const float* __restrict__ inten,
+                                                   int64_t count, float scale, int accumulate) {
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < count; i += (int64_t)gridDim.x * WG) {
+        const float v = scale * inten[i];
+        diff[i] = accumulate ? diff[i] + v : v;
+    }
+}
+
 template <int M>
 static hipError_t window_large(float2* win, float* inten, float* out, const int* perm, const int* bin_start,
                                const float2* tw_m, int n_probes, int n_bins, float scale, int accumulate,
                                hipStream_t st) {
-    // inten receives |Psi|^2 / M^4 (it is the 4D output when one is requested)
+    // inten receives |Psi|^2 / M^4 (it is the 4D output when one is requested
+    // unscaled and not accumulated)
     constexpr int G = 64 / Fft<M>::LPT;
     const int64_t rows = (int64_t)n_probes * M;
     hipLaunchKernelGGL((k_window_rows<M>), dim3((unsigned)((rows + 4 * G - 1) / (4 * G))), dim3(WG), 0, st, win,
@@ -729,12 +744,21 @@ hipError_t launch_window_batch(int m, const WindowArgs* jobs, int n_jobs, hipStr
         case 512:
             for (int k = 0; k < n_jobs; ++k) {
                 const WindowArgs& a = jobs[k];
-                float* I = a.diff ? a.diff : a.inten;
+                const bool direct = a.diff && a.scale == 1.0f && !a.accumulate;
+                float* I = direct ? a.diff : a.inten;
                 hipError_t e = m == 256 ? window_large<256>(a.win, I, a.out, a.perm, a.bin_start, a.tw_m,
                                                             a.n_probes, a.n_bins, a.scale, a.accumulate, st)
                                         : window_large<512>(a.win, I, a.out, a.perm, a.bin_start, a.tw_m,
                                                             a.n_probes, a.n_bins, a.scale, a.accumulate, st);
                 if (e != hipSuccess) return e;
+                if (a.diff && !direct) {
+                    const int64_t count = (int64_t)a.n_probes * m * m;
+                    const int64_t blocks = std::min<int64_t>((count + WG - 1) / WG, 65536);
+                    hipLaunchKernelGGL(k_scale_into, dim3((unsigned)blocks), dim3(WG), 0, st, a.diff, a.inten, count,
+                                       a.scale, a.accumulate);
+                    e = hipGetLastError();
+                    if (e != hipSuccess) return e;
+                }
             }
             return hipSuccess;
     }

@@ -505,3 +505,77 @@ def test_window_corners_bit_exact(P):
     ref = np.array([[(O.window_centre(x, L, w.n) - M // 2) % ns, (O.window_centre(y, L, w.n) - M // 2) % ns]
                     for x, y in xy], dtype=np.int32)
     assert np.array_equal(raw, ref)
+
+
+# ------------------------------------------------ batched-call regressions --
+def test_batched_split_when_first_job_on_an_s_matrix_has_no_probes(P):
+    """Jobs on one S-matrix share its split copy: it is converted when any of
+    them has probes, also when the first job has none."""
+    import torch
+    say("batched synthesis: empty job before a real one on the same S-matrix")
+    n, L, f = 256, 20.0, 2
+    g = P.prism_grid_init((L, L, 2.0), 2.0, n)
+    d = P.prism_smatrix_plan(g, 200e3, 0.02, f)
+    rng = np.random.default_rng(71)
+    S = torch.tensor(W.random_complex((d.n_beams, d.ns, d.ns), rng), device="cuda")
+    xy = W.random_positions((L, L), 9, rng)
+    empty = P.prism_probe_plan_upload(d, np.zeros((0, 2)))
+    plan = P.prism_probe_plan_upload(d, xy)
+    for prec in (P.PRISM_SPLIT_BF16X3, P.PRISM_BF16):
+        alone = P.prism_probe_outputs(d, S, plan, prec)
+        out0 = torch.empty((0, plan.plan.n_bins), dtype=torch.float32, device="cuda")
+        out1 = torch.full((len(xy), plan.plan.n_bins), float("nan"), dtype=torch.float32, device="cuda")
+        P.prism_probe_outputs_batched([(d, S, empty, out0), (d, S, plan, out1)], prec)
+        _sync()
+        assert torch.equal(out1, alone), prec
+
+
+@pytest.mark.parametrize("n,L,f,a", [(256, 20.0, 2, 0.02), (2048, 200.0, 2, 0.0015)])
+def test_batched_diffraction_scale_and_accumulate(P, n, L, f, a):
+    """The 4D output takes out_scale and accumulate as the 3D output does:
+    two configurations accumulated with scale 1/2 give their mean (windows of
+    64 and 512 pixels: the one-kernel and the large-window paths)."""
+    import torch
+    say(f"4D output averaged over two S-matrices, n={n} f={f}")
+    g = P.prism_grid_init((L, L, 2.0), 2.0, n)
+    d = P.prism_smatrix_plan(g, 200e3, a, f)
+    rng = np.random.default_rng(81 + n)
+    Ss = [torch.tensor(W.random_complex((d.n_beams, d.ns, d.ns), rng), device="cuda") for _ in range(2)]
+    xy = W.random_positions((L, L), 5, rng)
+    plan = P.prism_probe_plan_upload(d, xy)
+    M, nb = d.m_win, plan.plan.n_bins
+    single = [P.prism_probe_diffraction(d, S, plan, P.PRISM_FP32) for S in Ss]
+    single3 = [P.prism_probe_outputs(d, S, plan, P.PRISM_FP32) for S in Ss]
+    out = torch.full((len(xy), nb), 7.0, dtype=torch.float32, device="cuda")
+    diff = torch.full((len(xy), M, M), 7.0, dtype=torch.float32, device="cuda")
+    P.prism_probe_outputs_batched([(d, Ss[0], plan, out, diff, 0.5, 0)], P.PRISM_FP32)
+    P.prism_probe_outputs_batched([(d, Ss[1], plan, out, diff, 0.5, 1)], P.PRISM_FP32)
+    _sync()
+    mean4 = 0.5 * single[0].double() + 0.5 * single[1].double()
+    mean3 = 0.5 * single3[0].double() + 0.5 * single3[1].double()
+    e4 = (diff.double() - mean4).abs().max().item() / mean4.abs().max().item()
+    e3 = (out.double() - mean3).abs().max().item() / mean3.abs().max().item()
+    say(f"  M={M}: 4D mean err {e4:.2e}, 3D mean err {e3:.2e}")
+    assert e4 <= 1e-6 and e3 <= 1e-6
+
+
+def test_plan_upload_rejects_other_probes(P):
+    """A plan made for one position set does not upload for another whose
+    tile lists differ, even with the same number of entries and binned
+    pixels: a plan sized for at most one probe per tile must not take two
+    probes on the same tiles."""
+    import torch
+    g = P.prism_grid_init((32.0, 32.0, 4.0), 2.0, 256)
+    d = P.prism_smatrix_plan(g, 80e3, 0.02, 4)
+    a = np.array([[1.0, 1.0], [1.0, 1.0]])          # both windows on the same 9 tiles
+    b = np.array([[1.0, 1.0], [17.0, 17.0]])        # windows on disjoint tiles
+    pa = P.prism_probe_plan_init(d, a)
+    pb = P.prism_probe_plan_init(d, b)
+    assert pa.n_entries == pb.n_entries and pa.n_binned == pb.n_binned and pa.plan_bytes == pb.plan_bytes
+    assert (pa.max_per_tile, pb.max_per_tile) == (2, 1)
+    dev = torch.empty(pb.plan_bytes, dtype=torch.uint8, device="cuda")
+    ax = np.ascontiguousarray(a)
+    ct = P._lib.ctypes
+    rc = P.lib.prism_probe_plan_upload(ct.byref(d), ax.ctypes.data_as(ct.c_void_p), ct.byref(pb),
+                                       ct.c_void_p(dev.data_ptr()), None)
+    assert rc == P.PRISM_E_INVAL
