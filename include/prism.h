@@ -192,9 +192,36 @@ int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, i
                           prism_probe_plan* plan);
 
 /* Compute the plan tables and upload them into plan_dev (device, plan->plan_bytes).
- * Uploads host tables (waits for the copy on `stream`). */
+ * Uploads host tables (waits for the copy on `stream`).  The plan must have
+ * been made by prism_probe_plan_init for these positions: every size the
+ * kernels use (entries, tiles, largest probe count of a tile, binned pixels)
+ * is checked.  Errors: PRISM_E_INVAL (NULL, a plan for other positions or for
+ * a detector map), PRISM_E_DEVICE. */
 int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
                             const prism_probe_plan* plan, void* plan_dev, void* stream);
+
+/* Virtual detectors (Fig. 1e: detector outputs are sums of the diffraction
+ * intensity over detector regions; "Description of Algorithms": 2D, 3D or
+ * 4D outputs).  Instead of annular bins, the caller's detector map assigns
+ * each pixel of the probe window's Fourier grid to a detector:
+ * detector_map: host int32 [m_win][m_win], FFT order ([ky][kx], pitch f/L),
+ * entries -1 (no detector) or a detector index in [0, n_bins); any shape of
+ * detector (segments, inner/outer dark field, quadrants of a differential
+ * phase contrast detector).  n_bins in [1, 4096].  The plan records
+ * dalpha = 0.  out[p][b] of prism_probe_outputs is then the sum of
+ * |FFT_M(psi_p)|^2 / M^4 over the pixels mapped to b.  The map is read during
+ * the call only.  Errors: PRISM_E_INVAL (NULL map, an entry outside
+ * [-1, n_bins), n_bins outside [1, 4096]), as prism_probe_plan_init. */
+int prism_probe_plan_init_map(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes,
+                              const int32_t* detector_map, int32_t n_bins, const prism_aberrations* ab,
+                              prism_probe_plan* plan);
+
+/* prism_probe_plan_upload for a plan made by prism_probe_plan_init_map, with
+ * the same map.  Errors: as prism_probe_plan_upload; PRISM_E_INVAL for an
+ * annular plan or an invalid map. */
+int prism_probe_plan_upload_map(const prism_smatrix_desc* d, const double* probe_xy,
+                                const int32_t* detector_map, const prism_probe_plan* plan,
+                                void* plan_dev, void* stream);
 
 /* out[p][bin] (device float32 [n_probes][n_bins]) = sum over the bin's window
  * pixels of |FFT_M(psi_p)|^2 / M^4, where
@@ -263,6 +290,18 @@ int multislice_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes
 int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
                        const float* V, const double* probe_xy, int64_t n_probes, double dalpha,
                        int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* multislice_outputs with the caller's detector map over the n x n Fourier
+ * grid (host int32 [n][n], FFT order [ky][kx], pitch 1/L; entries -1 or a
+ * detector in [0, n_bins), n_bins in [1, 4096]) instead of annular bins:
+ * out[p][b] = sum over the pixels mapped to b of |Psi(q)|^2 / n^4 (pixels
+ * outside the propagator's band carry no intensity).  Uses the workspace of
+ * multislice_workspace.  Errors: as multislice_outputs; PRISM_E_INVAL for a
+ * NULL or invalid map. */
+int multislice_outputs_map(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                           const float* V, const double* probe_xy, int64_t n_probes,
+                           const int32_t* detector_map, int32_t n_bins, int32_t batch, float* out,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /* ---- streaming memory model ("Streaming Data for Very Large Simulations") --- */
 /* For cells whose potential or S-matrix should not be resident in device

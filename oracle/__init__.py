@@ -32,6 +32,6 @@ from .stem import (  # noqa: F401
     beam_set, probe_coefficients, aberration_phase,
     multislice_outputs, multislice_exit_spectrum,
     smatrix_layer, build_smatrix, smatrix_windows, prism_outputs_streamed,
-    window_centre, probe_window, prism_outputs, prism_diffraction, frozen_phonon_prism,
+    window_centre, probe_window, prism_outputs, prism_diffraction, frozen_phonon_prism, window_detector_map, detect,
     rel_err, adf_signal,
 )

@@ -264,15 +264,20 @@ def multislice_exit_spectrum(V, L: float, dz: float, lam: float, sigma: float,
 
 def multislice_outputs(V, L: float, dz: float, lam: float, sigma: float, alpha_max: float,
                        probe_xy, dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0,
-                       C3: float = 0.0, processes: int = 1):
+                       C3: float = 0.0, processes: int = 1, detector_map=None):
     """D[p][bin] = sum over bin of |Psi_exit|^2 / n^4 for each probe (3D output).
 
-    Probes are independent; `processes` > 1 runs them in forked worker
-    processes (same arithmetic per probe)."""
+    detector_map: optional [n][n] int detector index per Fourier pixel (FFT
+    order, -1 = none) with n_bins detectors, in place of annular bins (virtual
+    detectors, Fig. 1e).  Probes are independent; `processes` > 1 runs them in
+    forked worker processes (same arithmetic per probe)."""
     S, n, _ = V.shape
-    if n_bins is None:
-        n_bins = default_n_bins(lam, n, L, dalpha)
-    bmap = bin_map(lam, n, L, alpha_aa(lam, n, L), dalpha, n_bins)
+    if detector_map is not None:
+        bmap = np.asarray(detector_map)
+    else:
+        if n_bins is None:
+            n_bins = default_n_bins(lam, n, L, dalpha)
+        bmap = bin_map(lam, n, L, alpha_aa(lam, n, L), dalpha, n_bins)
     probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
 
     def one(p):
@@ -328,15 +333,26 @@ def probe_window(Smat, c, cx: int, cy: int, M: int):
     return np.tensordot(c, crop, axes=(0, 0))
 
 
-def prism_outputs(Smat, beams, L: float, n: int, lam: float, f: int, probe_xy,
-                  dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0, C3: float = 0.0):
-    """D[p][bin] for each probe from a compact S-matrix (3D output)."""
-    Ns = n // 2
-    M = Ns // f
-    Lw = L / f
+def window_detector_map(lam: float, n: int, L: float, f: int, dalpha: float, n_bins, detector_map):
+    """(map, n_bins) over the M x M window grid: the caller's map, or annular
+    bins of width dalpha up to alpha_AA."""
+    M = (n // 2) // f
+    if detector_map is not None:
+        return np.asarray(detector_map), n_bins
     if n_bins is None:
         n_bins = default_n_bins(lam, n, L, dalpha)
-    bmap = bin_map(lam, M, Lw, alpha_aa(lam, n, L), dalpha, n_bins)
+    return bin_map(lam, M, L / f, alpha_aa(lam, n, L), dalpha, n_bins), n_bins
+
+
+def prism_outputs(Smat, beams, L: float, n: int, lam: float, f: int, probe_xy,
+                  dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0, C3: float = 0.0,
+                  detector_map=None):
+    """D[p][bin] for each probe from a compact S-matrix (3D output);
+    detector_map: optional [M][M] detector index per window Fourier pixel (FFT
+    order, -1 = none) with n_bins detectors, in place of annular bins."""
+    Ns = n // 2
+    M = Ns // f
+    bmap, n_bins = window_detector_map(lam, n, L, f, dalpha, n_bins, detector_map)
     probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
     C = probe_coefficients(beams, L, probe_xy, lam, C1, C3)
     D = np.zeros((len(probe_xy), n_bins))
@@ -404,16 +420,13 @@ def smatrix_windows(t, P, beams, coeffs, centres, M: int):
 
 def prism_outputs_streamed(V, L: float, dz: float, lam: float, sigma: float, beams, n: int, f: int, probe_xy,
                            dalpha: float = 1e-3, n_bins: int | None = None, C1: float = 0.0, C3: float = 0.0,
-                           processes: int = 1, groups: int | None = None):
+                           processes: int = 1, groups: int | None = None, detector_map=None):
     """D[p][bin] of prism_outputs(build_smatrix(V, ...), ...) with the beams
     streamed through window accumulators; `groups` beam groups are summed in
     `processes` forked worker processes."""
     Ns = n // 2
     M = Ns // f
-    Lw = L / f
-    if n_bins is None:
-        n_bins = default_n_bins(lam, n, L, dalpha)
-    bmap = bin_map(lam, M, Lw, alpha_aa(lam, n, L), dalpha, n_bins)
+    bmap, n_bins = window_detector_map(lam, n, L, f, dalpha, n_bins, detector_map)
     probe_xy = np.atleast_2d(np.asarray(probe_xy, dtype=np.float64))
     t = transmission(V, sigma)
     P = propagator(n, L, lam, dz)

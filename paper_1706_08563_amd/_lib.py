@@ -79,6 +79,13 @@ _SIGNATURES = {
                                POINTER(prism_aberrations), POINTER(prism_probe_plan)], c_int32),
     "prism_probe_plan_upload": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p,
                                  c_void_p], c_int32),
+    "prism_probe_plan_init_map": ([POINTER(prism_smatrix_desc), c_void_p, c_int64, c_void_p, c_int32,
+                                   POINTER(prism_aberrations), POINTER(prism_probe_plan)], c_int32),
+    "prism_probe_plan_upload_map": ([POINTER(prism_smatrix_desc), c_void_p, c_void_p, POINTER(prism_probe_plan),
+                                     c_void_p, c_void_p], c_int32),
+    "multislice_outputs_map": ([POINTER(prism_grid), c_double, c_double, POINTER(prism_aberrations), c_void_p,
+                                c_void_p, c_int64, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_size_t,
+                                c_void_p], c_int32),
     "prism_probe_outputs": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p, c_int32,
                              c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "prism_probe_diffraction": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p, c_int32,

@@ -129,22 +129,43 @@ def _aberrations(C1, C3):
     return ctypes.byref(ab)
 
 
+def _map(detector_map, side):
+    m = np.ascontiguousarray(detector_map, dtype=np.int32)
+    if m.shape != (side, side):
+        raise ValueError(f"detector map must be int32 [{side}][{side}] (FFT order), got {m.shape}")
+    return m
+
+
 def prism_probe_plan_init(d: prism_smatrix_desc, xy, dalpha: float = 1e-3, n_bins: int = 0, C1: float = 0.0,
-                          C3: float = 0.0) -> prism_probe_plan:
+                          C3: float = 0.0, detector_map=None) -> prism_probe_plan:
+    """detector_map: optional int32 [m_win][m_win] (FFT order) virtual
+    detectors with n_bins detectors, in place of annular bins of width dalpha."""
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
     p = prism_probe_plan()
-    check(lib.prism_probe_plan_init(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha),
-                                    int(n_bins), _aberrations(C1, C3), ctypes.byref(p)))
+    if detector_map is None:
+        check(lib.prism_probe_plan_init(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha),
+                                        int(n_bins), _aberrations(C1, C3), ctypes.byref(p)))
+    else:
+        m = _map(detector_map, d.m_win)
+        check(lib.prism_probe_plan_init_map(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), len(xy),
+                                            m.ctypes.data_as(ctypes.c_void_p), int(n_bins), _aberrations(C1, C3),
+                                            ctypes.byref(p)))
     return p
 
 
 def prism_probe_plan_upload(d: prism_smatrix_desc, xy, dalpha: float = 1e-3, n_bins: int = 0,
-                            device=None, C1: float = 0.0, C3: float = 0.0) -> ProbePlan:
+                            device=None, C1: float = 0.0, C3: float = 0.0, detector_map=None) -> ProbePlan:
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
-    p = prism_probe_plan_init(d, xy, dalpha, n_bins, C1, C3)
+    p = prism_probe_plan_init(d, xy, dalpha, n_bins, C1, C3, detector_map)
     dev = _workspace(p.plan_bytes, device)
-    check(lib.prism_probe_plan_upload(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p),
-                                      _dev(dev), _stream()))
+    if detector_map is None:
+        check(lib.prism_probe_plan_upload(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p),
+                                          _dev(dev), _stream()))
+    else:
+        m = _map(detector_map, d.m_win)
+        check(lib.prism_probe_plan_upload_map(ctypes.byref(d), xy.ctypes.data_as(ctypes.c_void_p),
+                                              m.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), _dev(dev),
+                                              _stream()))
     return ProbePlan(p, dev, xy)
 
 
@@ -215,19 +236,28 @@ def multislice_workspace(grid: prism_grid, batch: int, n_probes: int) -> int:
 
 
 def multislice_outputs(grid: prism_grid, E0: float, alpha_max: float, V, xy, dalpha: float = 1e-3,
-                       n_bins: int = 0, batch: int = 64, ws=None, out=None, C1: float = 0.0, C3: float = 0.0):
-    """out [n_probes, n_bins] float32 on the device."""
+                       n_bins: int = 0, batch: int = 64, ws=None, out=None, C1: float = 0.0, C3: float = 0.0,
+                       detector_map=None):
+    """out [n_probes, n_bins] float32 on the device.  detector_map: optional
+    int32 [n][n] (FFT order) virtual detectors with n_bins detectors."""
     torch = _torch()
     xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
-    if n_bins <= 0:
+    if detector_map is None and n_bins <= 0:
         n_bins = prism_detector_default_bins(grid, E0, dalpha)[0]
     if ws is None:
         ws = _workspace(multislice_workspace(grid, batch, len(xy)), V.device)
     if out is None:
         out = torch.empty((len(xy), n_bins), dtype=torch.float32, device=V.device)
-    check(lib.multislice_outputs(ctypes.byref(grid), float(E0), float(alpha_max), _aberrations(C1, C3), _dev(V),
-                                 xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha), int(n_bins), int(batch),
-                                 _dev(out), _dev(ws), ws.numel(), _stream()))
+    if detector_map is None:
+        check(lib.multislice_outputs(ctypes.byref(grid), float(E0), float(alpha_max), _aberrations(C1, C3), _dev(V),
+                                     xy.ctypes.data_as(ctypes.c_void_p), len(xy), float(dalpha), int(n_bins),
+                                     int(batch), _dev(out), _dev(ws), ws.numel(), _stream()))
+    else:
+        m = _map(detector_map, grid.n)
+        check(lib.multislice_outputs_map(ctypes.byref(grid), float(E0), float(alpha_max), _aberrations(C1, C3),
+                                         _dev(V), xy.ctypes.data_as(ctypes.c_void_p), len(xy),
+                                         m.ctypes.data_as(ctypes.c_void_p), int(n_bins), int(batch), _dev(out),
+                                         _dev(ws), ws.numel(), _stream()))
     return out
 
 

@@ -131,6 +131,7 @@ inline int centre_of(double x, double L, int n) {
 }
 
 int default_bins(double a_aa, double dalpha) { return (int)std::ceil(a_aa / dalpha); }
+constexpr int MAX_BINS = 4096;   // detector bins of one output (multislice workspace bound)
 
 // exp(-i chi(q)), chi = pi lam C1 q^2 + (pi/2) C3 lam^3 q^4, q = k/L: the phase
 // is formed and reduced mod 2 pi in FP64, the factor stored in FP32.
@@ -243,28 +244,45 @@ struct ProbeHost {
     std::vector<float2> aberr;      // per beam, empty when there are no aberrations
 };
 
-// Detector tables: pixels (index ky_i * m + kx_i of an m x m FFT-order grid)
-// grouped by bin, ascending pixel index inside a bin.
-void bin_tables(double lam, double Lw, double a_aa, double dalpha, int n_bins, int m, std::vector<int>& perm,
-                std::vector<int>& start) {
+// Detector tables: pixel indices grouped by bin (bins[i] in [-1, n_bins),
+// -1 = no bin), ascending pixel index inside a bin; start[b] .. start[b+1]
+// delimit bin b in perm.
+void group_by_bin(const std::vector<int>& bins, int n_bins, std::vector<int>& perm, std::vector<int>& start) {
     std::vector<int> cnt(n_bins + 1, 0);
-    std::vector<int> bins((size_t)m * m);
-    for (int r = 0; r < m; ++r)
-        for (int c = 0; c < m; ++c) {
-            int b = bin_of(lam, freq(c, m), freq(r, m), Lw, a_aa, dalpha, n_bins);
-            bins[(size_t)r * m + c] = b;
-            if (b >= 0) cnt[b + 1]++;
-        }
+    for (int b : bins)
+        if (b >= 0) cnt[b + 1]++;
     start.assign(n_bins + 1, 0);
     for (int b = 0; b < n_bins; ++b) start[b + 1] = start[b] + cnt[b + 1];
     perm.assign(start[n_bins], 0);
     std::vector<int> fill(start.begin(), start.end() - 1);
-    for (int i = 0; i < m * m; ++i)
-        if (bins[i] >= 0) perm[fill[bins[i]]++] = i;
+    for (size_t i = 0; i < bins.size(); ++i)
+        if (bins[i] >= 0) perm[fill[bins[i]]++] = (int)i;
+}
+
+// Annular bins of an m x m FFT-order grid (pixel index ky_i * m + kx_i), or
+// the caller's detector map of that grid when `dmap` is given.
+void bin_tables(double lam, double Lw, double a_aa, double dalpha, int n_bins, int m, const int32_t* dmap,
+                std::vector<int>& perm, std::vector<int>& start) {
+    std::vector<int> bins((size_t)m * m);
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c)
+            bins[(size_t)r * m + c] =
+                dmap ? dmap[(size_t)r * m + c] : bin_of(lam, freq(c, m), freq(r, m), Lw, a_aa, dalpha, n_bins);
+    group_by_bin(bins, n_bins, perm, start);
+}
+
+// A caller's detector map: every entry -1 (no detector) or a bin in [0, n_bins).
+int check_detector_map(const int32_t* dmap, size_t count, int n_bins, const char* what) {
+    if (!dmap) return fail(PRISM_E_INVAL, "%s: NULL detector map", what);
+    if (n_bins < 1 || n_bins > MAX_BINS) return fail(PRISM_E_INVAL, "%s: n_bins %d outside [1, %d]", what, n_bins, MAX_BINS);
+    for (size_t i = 0; i < count; ++i)
+        if (dmap[i] < -1 || dmap[i] >= n_bins)
+            return fail(PRISM_E_INVAL, "%s: detector map entry %zu = %d outside [-1, %d)", what, i, (int)dmap[i], n_bins);
+    return PRISM_OK;
 }
 
 int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, double dalpha, int n_bins,
-               double C1, double C3, ProbeHost& h, int& max_per_tile) {
+               double C1, double C3, const int32_t* dmap, ProbeHost& h, int& max_per_tile) {
     const int n = d->grid.n, ns = d->ns, M = d->m_win;
     const double L = d->grid.cell[0];
     const int ntx = ns / 16, n_tiles = ntx * ntx;
@@ -306,7 +324,7 @@ int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, 
                 for (int tx = 0; tx < ntx; ++tx)
                     if (mark_x[tx]) h.tile_probes[fill[ty * ntx + tx]++] = (int)p;
     }
-    bin_tables(d->lambda, L / d->f, d->alpha_aa, dalpha, n_bins, M, h.perm, h.bin_start);
+    bin_tables(d->lambda, L / d->f, d->alpha_aa, dalpha, n_bins, M, dmap, h.perm, h.bin_start);
     h.tw_m = twiddle_table(M);
     h.beams = beam_list(n, L, d->lambda, d->alpha_max, d->f);
     h.aberr.clear();
@@ -669,18 +687,26 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
 }
 
 // -------------------------------------------------------- probe outputs --
-int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes, double dalpha,
-                          int32_t n_bins, const prism_aberrations* ab, prism_probe_plan* plan) {
+// Plan of either detector: annular bins of width dalpha (dmap NULL) or the
+// caller's map of the window grid (dalpha recorded as 0).
+static int probe_plan_make(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes, double dalpha,
+                           int32_t n_bins, const int32_t* dmap, const prism_aberrations* ab, prism_probe_plan* plan) {
     int rc = check_desc(d);
     if (rc) return rc;
-    if (!plan || (n_probes > 0 && !probe_xy) || n_probes < 0 || n_probes > (1 << 30) || !(dalpha > 0))
+    if (!plan || (n_probes > 0 && !probe_xy) || n_probes < 0 || n_probes > (1 << 30) || (!dmap && !(dalpha > 0)))
         return fail(PRISM_E_INVAL, "probe plan: invalid argument");
     const double C1 = ab ? ab->C1 : 0.0, C3 = ab ? ab->C3 : 0.0;
     if (!std::isfinite(C1) || !std::isfinite(C3)) return fail(PRISM_E_INVAL, "probe plan: non-finite aberrations");
-    if (n_bins <= 0) n_bins = default_bins(d->alpha_aa, dalpha);
+    if (dmap) {
+        rc = check_detector_map(dmap, (size_t)d->m_win * d->m_win, n_bins, "probe plan");
+        if (rc) return rc;
+        dalpha = 0.0;
+    } else if (n_bins <= 0) {
+        n_bins = default_bins(d->alpha_aa, dalpha);
+    }
     ProbeHost h;
     int maxpt = 0;
-    rc = probe_host(d, probe_xy, n_probes, dalpha, n_bins, C1, C3, h, maxpt);
+    rc = probe_host(d, probe_xy, n_probes, dalpha, n_bins, C1, C3, dmap, h, maxpt);
     if (rc) return rc;
     prism_probe_plan p{};
     p.n_probes = n_probes;
@@ -712,14 +738,34 @@ int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, i
     return PRISM_OK;
 }
 
-int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy, const prism_probe_plan* plan,
-                            void* plan_dev, void* stream) {
+int prism_probe_plan_init(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes, double dalpha,
+                          int32_t n_bins, const prism_aberrations* ab, prism_probe_plan* plan) {
+    return probe_plan_make(d, probe_xy, n_probes, dalpha, n_bins, nullptr, ab, plan);
+}
+
+int prism_probe_plan_init_map(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes,
+                              const int32_t* detector_map, int32_t n_bins, const prism_aberrations* ab,
+                              prism_probe_plan* plan) {
+    if (!detector_map) return fail(PRISM_E_INVAL, "probe plan: NULL detector map");
+    return probe_plan_make(d, probe_xy, n_probes, 0.0, n_bins, detector_map, ab, plan);
+}
+
+static int probe_plan_put(const prism_smatrix_desc* d, const double* probe_xy, const int32_t* dmap,
+                          const prism_probe_plan* plan, void* plan_dev, void* stream) {
     int rc = check_desc(d);
     if (rc) return rc;
     if (!plan || !plan_dev) return fail(PRISM_E_INVAL, "probe plan upload: NULL argument");
+    if (dmap) {
+        if (plan->dalpha != 0.0)
+            return fail(PRISM_E_INVAL, "probe plan upload: the plan has annular bins; upload it without a map");
+        rc = check_detector_map(dmap, (size_t)d->m_win * d->m_win, plan->n_bins, "probe plan upload");
+        if (rc) return rc;
+    } else if (!(plan->dalpha > 0)) {
+        return fail(PRISM_E_INVAL, "probe plan upload: the plan was made for a detector map; upload it with that map");
+    }
     ProbeHost h;
     int maxpt = 0;
-    rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, plan->C1, plan->C3, h, maxpt);
+    rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, plan->C1, plan->C3, dmap, h, maxpt);
     if (rc) return rc;
     // every size the kernels and the workspace depend on must be the plan's
     if ((int64_t)h.tile_probes.size() != plan->n_entries || (int)h.perm.size() != plan->n_binned ||
@@ -739,6 +785,17 @@ int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy,
     put(plan->off[7], h.beams.data(), h.beams.size() * sizeof(int2));
     if (!h.aberr.empty()) put(plan->off[8], h.aberr.data(), h.aberr.size() * sizeof(float2));
     return upload(plan_dev, blob, as_stream(stream));
+}
+
+int prism_probe_plan_upload(const prism_smatrix_desc* d, const double* probe_xy, const prism_probe_plan* plan,
+                            void* plan_dev, void* stream) {
+    return probe_plan_put(d, probe_xy, nullptr, plan, plan_dev, stream);
+}
+
+int prism_probe_plan_upload_map(const prism_smatrix_desc* d, const double* probe_xy, const int32_t* detector_map,
+                                const prism_probe_plan* plan, void* plan_dev, void* stream) {
+    if (!detector_map) return fail(PRISM_E_INVAL, "probe plan upload: NULL detector map");
+    return probe_plan_put(d, probe_xy, detector_map, plan, plan_dev, stream);
 }
 
 // Index of the first job that reads the same S-matrix (same pointer and shape).
@@ -893,7 +950,8 @@ struct MsHost {
 };
 
 static int multislice_host(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
-                           const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins, MsHost& h) {
+                           const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins,
+                           const int32_t* dmap, MsHost& h) {
     const int n = grid->n, Lh = n / 2;
     const double L = grid->cell[0];
     h.lam = wavelength_A(E0);
@@ -901,8 +959,13 @@ static int multislice_host(const prism_grid* grid, double E0, double alpha_max, 
     h.a_aa = alpha_aa_of(h.lam, n, L);
     if (!(alpha_max < h.a_aa))
         return fail(PRISM_E_UNSUPPORTED, "multislice: alpha_max %.6g must be below alpha_AA %.6g", alpha_max, h.a_aa);
-    if (n_bins <= 0) n_bins = default_bins(h.a_aa, dalpha);
-    if (n_bins > 4096) return fail(PRISM_E_UNSUPPORTED, "multislice: more than 4096 bins");
+    if (dmap) {
+        int rc = check_detector_map(dmap, (size_t)n * n, n_bins, "multislice");
+        if (rc) return rc;
+    } else if (n_bins <= 0) {
+        n_bins = default_bins(h.a_aa, dalpha);
+    }
+    if (n_bins > MAX_BINS) return fail(PRISM_E_UNSUPPORTED, "multislice: more than %d bins", MAX_BINS);
     h.n_bins = n_bins;
     // aperture per band column and its size
     h.kymax.assign(Lh, -1);
@@ -924,22 +987,17 @@ static int multislice_host(const prism_grid* grid, double E0, double alpha_max, 
             for (int jp = 0; jp < Lh; ++jp)
                 h.aberr[(size_t)j * Lh + jp] = aberration_factor(band_k(j, n), band_k(jp, n), L, h.lam, C1, C3);
     }
-    // bins over band pixels, index j * (n/2) + j' (kx from j, ky from j')
-    std::vector<int> cnt(n_bins + 1, 0), bins((size_t)Lh * Lh);
+    // bins over band pixels, index j * (n/2) + j' (kx from j, ky from j');
+    // the band holds every pixel of nonzero intensity (the propagator's
+    // mask), so a map's entries outside it add nothing
+    std::vector<int> bins((size_t)Lh * Lh);
     for (int j = 0; j < Lh; ++j)
         for (int jp = 0; jp < Lh; ++jp) {
-            int b = bin_of(h.lam, band_k(j, n), band_k(jp, n), L, h.a_aa, dalpha, n_bins);
-            bins[(size_t)j * Lh + jp] = b;
-            if (b >= 0) cnt[b + 1]++;
+            const int kx = band_k(j, n), ky = band_k(jp, n);
+            bins[(size_t)j * Lh + jp] = dmap ? dmap[(size_t)((ky + n) % n) * n + (kx + n) % n]
+                                             : bin_of(h.lam, kx, ky, L, h.a_aa, dalpha, n_bins);
         }
-    h.bstart.assign(n_bins + 1, 0);
-    for (int b = 0; b < n_bins; ++b) h.bstart[b + 1] = h.bstart[b] + cnt[b + 1];
-    h.perm.resize(h.bstart[n_bins]);
-    {
-        std::vector<int> fill(h.bstart.begin(), h.bstart.end() - 1);
-        for (size_t i = 0; i < bins.size(); ++i)
-            if (bins[i] >= 0) h.perm[fill[bins[i]]++] = (int)i;
-    }
+    group_by_bin(bins, n_bins, h.perm, h.bstart);
     h.xy.resize(std::max<int64_t>(n_probes, 1));
     for (int64_t p = 0; p < n_probes; ++p) {
         if (!std::isfinite(probe_xy[2 * p]) || !std::isfinite(probe_xy[2 * p + 1]))
@@ -982,7 +1040,7 @@ static int multislice_ws(const prism_grid* grid, int32_t batch, int64_t n_probes
     Carve c(nullptr);
     MsDev m;
     // bins can cover at most the (n/2)^2 band pixels
-    multislice_carve(c, grid->n, grid->n_slices, n_probes, batch, 4096, (size_t)(grid->n / 2) * (grid->n / 2),
+    multislice_carve(c, grid->n, grid->n_slices, n_probes, batch, MAX_BINS, (size_t)(grid->n / 2) * (grid->n / 2),
                      streaming, m);
     *bytes = c.off + 256;
     return PRISM_OK;
@@ -1048,19 +1106,19 @@ static int join_ring(const Ring2& r, bool on_freed, hipStream_t st) {
 
 static int multislice_run(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
                           const float* V, const float* V_host, const double* probe_xy, int64_t n_probes,
-                          double dalpha, int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes,
-                          hipStream_t st, hipStream_t h2d) {
+                          double dalpha, int32_t n_bins, const int32_t* dmap, int32_t batch, float* out, void* ws,
+                          size_t ws_bytes, hipStream_t st, hipStream_t h2d) {
     int rc = check_grid(grid);
     if (rc) return rc;
     const bool streaming = V_host != nullptr;
     if ((!V && !V_host) || (!out && n_probes > 0) || (n_probes > 0 && !probe_xy) || n_probes < 0 || batch < 1 ||
         !(E0 > 0) ||
-        !(alpha_max > 0) || !(dalpha > 0))
+        !(alpha_max > 0) || (!dmap && !(dalpha > 0)))
         return fail(PRISM_E_INVAL, "multislice: invalid argument");
     const int n = grid->n, Lh = n / 2, nsl = grid->n_slices;
     const double L = grid->cell[0];
     MsHost h;
-    rc = multislice_host(grid, E0, alpha_max, ab, probe_xy, n_probes, dalpha, n_bins, h);
+    rc = multislice_host(grid, E0, alpha_max, ab, probe_xy, n_probes, dalpha, n_bins, dmap, h);
     if (rc) return rc;
     n_bins = h.n_bins;
     size_t need = 0;
@@ -1128,8 +1186,17 @@ int multislice_outputs(const prism_grid* grid, double E0, double alpha_max, cons
                        const float* V, const double* probe_xy, int64_t n_probes, double dalpha, int32_t n_bins,
                        int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream) {
     if (!V) return fail(PRISM_E_INVAL, "multislice: NULL V");
-    return multislice_run(grid, E0, alpha_max, ab, V, nullptr, probe_xy, n_probes, dalpha, n_bins, batch, out, ws,
-                          ws_bytes, as_stream(stream), nullptr);
+    return multislice_run(grid, E0, alpha_max, ab, V, nullptr, probe_xy, n_probes, dalpha, n_bins, nullptr, batch,
+                          out, ws, ws_bytes, as_stream(stream), nullptr);
+}
+
+int multislice_outputs_map(const prism_grid* grid, double E0, double alpha_max, const prism_aberrations* ab,
+                           const float* V, const double* probe_xy, int64_t n_probes, const int32_t* detector_map,
+                           int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!V) return fail(PRISM_E_INVAL, "multislice: NULL V");
+    if (!detector_map) return fail(PRISM_E_INVAL, "multislice: NULL detector map");
+    return multislice_run(grid, E0, alpha_max, ab, V, nullptr, probe_xy, n_probes, 0.0, n_bins, detector_map, batch,
+                          out, ws, ws_bytes, as_stream(stream), nullptr);
 }
 
 int multislice_streaming_workspace(const prism_grid* grid, int32_t batch, int64_t n_probes, size_t* bytes) {
@@ -1141,8 +1208,8 @@ int multislice_outputs_streaming(const prism_grid* grid, double E0, double alpha
                                  int32_t n_bins, int32_t batch, float* out, void* ws, size_t ws_bytes, void* stream,
                                  void* h2d_stream) {
     if (!V_host) return fail(PRISM_E_INVAL, "multislice streaming: NULL V_host");
-    return multislice_run(grid, E0, alpha_max, ab, nullptr, V_host, probe_xy, n_probes, dalpha, n_bins, batch, out,
-                          ws, ws_bytes, as_stream(stream), as_stream(h2d_stream));
+    return multislice_run(grid, E0, alpha_max, ab, nullptr, V_host, probe_xy, n_probes, dalpha, n_bins, nullptr,
+                          batch, out, ws, ws_bytes, as_stream(stream), as_stream(h2d_stream));
 }
 
 // ----------------------------------------------------- streaming S-matrix --

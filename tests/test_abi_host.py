@@ -182,3 +182,35 @@ def test_device_copy_argument_checks():
     assert lib.prism_device_copy(ctypes.c_void_p(aligned + 4), ctypes.c_void_p(aligned + 32), 16, None) == P.PRISM_E_INVAL
     assert lib.prism_device_copy(ctypes.c_void_p(aligned), ctypes.c_void_p(aligned + 16), 32, None) == P.PRISM_E_INVAL
     assert lib.prism_device_copy(ctypes.c_void_p(aligned), ctypes.c_void_p(aligned + 16), 0, None) == P.PRISM_OK
+
+
+def test_detector_map_plans_and_validation():
+    """Plans with a caller's detector map: binned pixel count is the map's
+    mapped pixels; entries outside [-1, n_bins) and maps of the wrong side are
+    refused; annular and map plans do not upload for each other."""
+    P = _lib()
+    w = W.WORKLOADS["prism_f2_sc_256"]
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    xy = W.scan_positions(w.cell, 4, 4)
+    M = d.m_win
+    rng = np.random.default_rng(5)
+    dmap = rng.integers(-1, 7, size=(M, M)).astype(np.int32)
+    p = P.prism_probe_plan_init(d, xy, n_bins=7, detector_map=dmap)
+    assert p.n_bins == 7 and p.dalpha == 0.0 and p.n_binned == int((dmap >= 0).sum())
+    for bad, nb in ((np.where(dmap == 3, 7, dmap), 7), (np.where(dmap == 3, -2, dmap), 7), (dmap, 0)):
+        with pytest.raises(P.PrismError) as e:
+            P.prism_probe_plan_init(d, xy, n_bins=nb, detector_map=bad)
+        assert e.value.code == P.PRISM_E_INVAL
+    with pytest.raises(ValueError):
+        P.prism_probe_plan_init(d, xy, n_bins=7, detector_map=dmap[:-1])
+    ct = P._lib.ctypes
+    pa = P.prism_probe_plan_init(d, xy)
+    fake = ct.c_void_p(0x1000)           # never dereferenced: the calls fail on their arguments first
+    xyc = np.ascontiguousarray(xy)
+    dm = np.ascontiguousarray(dmap)
+    assert P.lib.prism_probe_plan_upload_map(ct.byref(d), xyc.ctypes.data_as(ct.c_void_p),
+                                             dm.ctypes.data_as(ct.c_void_p), ct.byref(pa), fake, None) \
+        == P.PRISM_E_INVAL
+    assert P.lib.prism_probe_plan_upload(ct.byref(d), xyc.ctypes.data_as(ct.c_void_p), ct.byref(p), fake, None) \
+        == P.PRISM_E_INVAL

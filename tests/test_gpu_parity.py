@@ -579,3 +579,41 @@ def test_plan_upload_rejects_other_probes(P):
     rc = P.lib.prism_probe_plan_upload(ct.byref(d), ax.ctypes.data_as(ct.c_void_p), ct.byref(pb),
                                        ct.c_void_p(dev.data_ptr()), None)
     assert rc == P.PRISM_E_INVAL
+
+
+# -------------------------------------------------------- virtual detectors --
+def _segments(m, n_rings=3):
+    """Quadrant segments of rings plus an off-centre disc (see the oracle pins)."""
+    from test_oracle_pins import _segment_map
+    return _segment_map(m, n_rings)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_virtual_detectors_prism_and_multislice(P, prec):
+    """A segmented, non-annular detector map (ring quadrants and an
+    off-centre disc) on PRISM f = 2 and on multislice, scattering cell,
+    against the oracle with the same map."""
+    say(f"virtual detectors: segmented map, PRISM f=2 (precision {prec}) and multislice")
+    w, pos, sp = W.small_workload(n=128, cell=(16.0, 16.0, 6.0), n_atoms=40, f=2, seed=19)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    S = P.prism_build_smatrix(d, V)
+    xy = np.concatenate([W.scan_positions(w.cell, 3, 3), [[-2.0, 17.5]]])
+    wmap, nb = _segments(d.m_win)
+    plan = P.prism_probe_plan_upload(d, xy, n_bins=nb, detector_map=wmap)
+    out = P.prism_probe_outputs(d, S, plan, prec)
+    nmap, nbm = _segments(w.n, 4)
+    ms = P.multislice_outputs(g, w.E0, w.alpha_max, V, xy, n_bins=nbm, batch=4, detector_map=nmap)
+    _sync()
+    L = w.cell[0]
+    Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    beams = O.beam_set(w.n, L, lam, w.alpha_max, w.f)
+    Sref = O.build_smatrix(Vref, L, w.dz, lam, sig, beams)
+    ref = O.prism_outputs(Sref, beams, L, w.n, lam, w.f, xy, detector_map=wmap, n_bins=nb)
+    mref = O.multislice_outputs(Vref, L, w.dz, lam, sig, w.alpha_max, xy, detector_map=nmap, n_bins=nbm)
+    check_D(out.cpu().numpy(), ref, "segmented PRISM")
+    check_D(ms.cpu().numpy(), mref, "segmented multislice")
+    # the map is not annular: the quadrants of a ring differ for an off-axis probe
+    got = out.cpu().numpy()
+    assert np.max(np.abs(got[:, 4] - got[:, 5])) > 1e-6

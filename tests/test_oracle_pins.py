@@ -622,3 +622,76 @@ def test_prism_streamed_f1_equals_multislice_and_stored_form():
     streamed = O.prism_outputs_streamed(V, L, w.dz, lam, sig, b2, w.n, 2, xy, processes=2, groups=5)
     assert O.rel_err(streamed, stored) < 1e-13
     assert O.rel_err(stored, Dm) > 1e-4      # f = 2 differs from multislice: the check is not vacuous
+
+
+# ---------------------------------------------------------------------------
+# Virtual detectors (Fig. 1e): a caller's detector map in place of annular
+# bins.  detect() against hand sums; the vacuum closed form generalised to any
+# map (the beams' pixels carry 1/|B| each); the annular map given explicitly
+# reproduces the default output.
+# ---------------------------------------------------------------------------
+def test_detect_hand_sums():
+    I = (2.0 ** np.arange(16)).reshape(4, 4)
+    bmap = np.array([[0, 0, 1, -1], [2, 1, 1, -1], [-1, -1, 2, 0], [3, 3, 3, 3]])
+    D = O.detect(I, bmap, 5)
+    assert D.tolist() == [1 + 2 + 2 ** 11, 4 + 32 + 64, 16 + 2 ** 10, 2 ** 12 + 2 ** 13 + 2 ** 14 + 2 ** 15, 0.0]
+
+
+def _segment_map(m, n_rings=3):
+    """Quadrant segments of rings of the m x m FFT-order grid plus an
+    off-centre disc: detector 4 r + quadrant for ring r, 4 n_rings for the disc."""
+    k = O.fourier_indices(m)
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    r = np.sqrt(kx * kx + ky * ky)
+    ring = np.floor(r / (m / (2.0 * n_rings))).astype(int)
+    quad = (kx >= 0).astype(int) + 2 * (ky >= 0).astype(int)
+    out = np.where(ring < n_rings, 4 * ring + quad, -1)
+    disc = (kx - m // 8) ** 2 + (ky + m // 16) ** 2 <= (m // 16) ** 2
+    out[disc] = 4 * n_rings
+    return out.astype(np.int32), 4 * n_rings + 1
+
+
+@pytest.mark.parametrize("f", [1, 2])
+def test_virtual_detector_vacuum_closed_form(f):
+    n, L, E0, a = 64, 10.0, 80e3, 0.02
+    lam, sig = O.wavelength(E0), O.interaction_constant(E0)
+    beams = O.beam_set(n, L, lam, a, f)
+    M = n // 2 // f
+    dmap, nb = _segment_map(M)
+    xy = np.array([[0.0, 0.0], [3.3, 7.1], [9.9, 0.2]])
+    S = O.build_smatrix(np.zeros((2, n, n)) + 1.5, L, 2.0, lam, sig, beams)
+    D = O.prism_outputs(S, beams, L, n, lam, f, xy, detector_map=dmap, n_bins=nb)
+    # each beam lands on window pixel (kx/f, ky/f) with intensity 1/|B|
+    exp = np.zeros(nb)
+    for kx, ky in beams:
+        d = dmap[(ky // f) % M, (kx // f) % M]
+        if d >= 0:
+            exp[d] += 1.0 / len(beams)
+    assert np.max(np.abs(D - exp[None, :])) < 1e-13
+    assert exp.min() == 0.0 and np.count_nonzero(exp) >= 4     # several detectors lit, some dark
+    if f == 1:
+        nmap, nbm = _segment_map(n)
+        Dm = O.multislice_outputs(np.zeros((2, n, n)) + 1.5, L, 2.0, lam, sig, a, xy, detector_map=nmap,
+                                  n_bins=nbm)
+        expm = np.zeros(nbm)
+        for kx, ky in beams:
+            if nmap[ky % n, kx % n] >= 0:
+                expm[nmap[ky % n, kx % n]] += 1.0 / len(beams)
+        assert np.max(np.abs(Dm - expm[None, :])) < 1e-13
+
+
+def test_virtual_detector_annular_map_equals_default():
+    w, pos, sp = W.small_workload(n=64, n_atoms=16, seed=5)
+    lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
+    V = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
+    L, n, f = w.cell[0], w.n, 2
+    xy = np.array([[0.0, 0.0], [2.5, 7.5]])
+    beams = O.beam_set(n, L, lam, w.alpha_max, f)
+    S = O.build_smatrix(V, L, w.dz, lam, sig, beams)
+    nb = O.default_n_bins(lam, n, L, 1e-3)
+    amap = O.bin_map(lam, n // 2 // f, L / f, O.alpha_aa(lam, n, L), 1e-3, nb)
+    assert np.array_equal(O.prism_outputs(S, beams, L, n, lam, f, xy, detector_map=amap, n_bins=nb),
+                          O.prism_outputs(S, beams, L, n, lam, f, xy))
+    nmap = O.bin_map(lam, n, L, O.alpha_aa(lam, n, L), 1e-3, nb)
+    assert np.array_equal(O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy, detector_map=nmap, n_bins=nb),
+                          O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy))
