@@ -23,7 +23,9 @@
  *     pointers documented as "host" are read during the call only.  The
  *     library allocates no device memory: scratch space comes in through a
  *     caller-provided workspace whose size the *_plan / *_workspace call
- *     reports.  `stream` is a hipStream_t (NULL = the default stream).
+ *     reports (prism_probe_outputs_noalloc alone uses the library's fixed
+ *     scratch array instead).  `stream` is a hipStream_t (NULL = the default
+ *     stream).
  *   - Execution: work is queued on `stream` and the call returns without
  *     waiting for it, except where a function says it uploads host tables:
  *     those calls copy small host-computed tables into the workspace and wait
@@ -233,6 +235,22 @@ int prism_probe_outputs(const prism_smatrix_desc* d, const void* S,
                         const prism_probe_plan* plan, const void* plan_dev,
                         int32_t precision, float* out,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * prism_probe_outputs with the same kernels and result, its workspace taken
+ * from a fixed scratch array of PRISM_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends.  The caller passes the
+ * inputs (S, the uploaded plan) and the output as for prism_probe_outputs.
+ * The call allocates nothing on the device.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (on different streams or
+ * from different threads) race and must not be issued.  Fully asynchronous.
+ * Errors: PRISM_E_WORKSPACE when the plan's workspace (plan->ws_bytes)
+ * exceeds PRISM_NOALLOC_SCRATCH_BYTES; otherwise as prism_probe_outputs. */
+#define PRISM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int prism_probe_outputs_noalloc(const prism_smatrix_desc* d, const void* S,
+                                const prism_probe_plan* plan, const void* plan_dev,
+                                int32_t precision, float* out, void* stream);
 
 /* 4D output (Fig. 1e/k, "the entire probe diffraction pattern"):
  * out4d[p][ky][kx] (device float32 [n_probes][m_win][m_win], FFT order on the

@@ -7,7 +7,7 @@ the library has not been built.
 """
 from ._lib import (  # noqa: F401
     PRISM_OK, PRISM_E_INVAL, PRISM_E_UNSUPPORTED, PRISM_E_NOMEM, PRISM_E_DEVICE, PRISM_E_WORKSPACE,
-    PRISM_FP32, PRISM_SPLIT_BF16X3, PRISM_BF16, PrismError, EXPORTED, LIB_PATH,
+    PRISM_FP32, PRISM_SPLIT_BF16X3, PRISM_BF16, PRISM_NOALLOC_SCRATCH_BYTES, PrismError, EXPORTED, LIB_PATH,
     prism_atom, prism_species, prism_grid, prism_smatrix_desc, prism_probe_plan, prism_probe_job, TIMING_CLASSES,
 )
 from .api import (  # noqa: F401
@@ -19,6 +19,6 @@ from .api import (  # noqa: F401
     prism_streaming_build_workspace, prism_build_smatrix_streaming, prism_probe_streaming_workspace,
     prism_probe_outputs_streaming, multislice_streaming_workspace, multislice_outputs_streaming,
     prism_probe_chunked_workspace, prism_probe_outputs_chunked, prism_set_build_streams,
-    prism_device_copy,
+    prism_device_copy, prism_probe_outputs_noalloc,
 )
 from . import _lib  # noqa: F401

@@ -22,6 +22,8 @@ PRISM_FP32 = 0
 PRISM_SPLIT_BF16X3 = 1
 PRISM_BF16 = 2
 
+PRISM_NOALLOC_SCRATCH_BYTES = 64 << 20   # fixed scratch of prism_probe_outputs_noalloc
+
 
 class prism_atom(ctypes.Structure):
     _fields_ = [("x", c_double), ("y", c_double), ("z", c_double), ("species", c_int32), ("pad", c_int32)]
@@ -88,6 +90,8 @@ _SIGNATURES = {
                                 c_void_p], c_int32),
     "prism_probe_outputs": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p, c_int32,
                              c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
+    "prism_probe_outputs_noalloc": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p,
+                                     c_int32, c_void_p, c_void_p], c_int32),
     "prism_probe_diffraction": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p, c_int32,
                                  c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "prism_probe_batch_workspace": ([POINTER(prism_probe_job), c_int32, POINTER(c_size_t)], c_int32),

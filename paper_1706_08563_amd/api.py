@@ -182,6 +182,18 @@ def prism_probe_outputs(d: prism_smatrix_desc, S, plan: ProbePlan, precision: in
     return out
 
 
+def prism_probe_outputs_noalloc(d: prism_smatrix_desc, S, plan: ProbePlan, precision: int = PRISM_FP32, out=None):
+    """prism_probe_outputs with the library's fixed device scratch as its
+    workspace (no device allocation inside the call; `out` may be given)."""
+    torch = _torch()
+    p = plan.plan
+    if out is None:
+        out = torch.empty((p.n_probes, p.n_bins), dtype=torch.float32, device=S.device)
+    check(lib.prism_probe_outputs_noalloc(ctypes.byref(d), _dev(S), ctypes.byref(p), _dev(plan.dev), int(precision),
+                                          _dev(out), _stream()))
+    return out
+
+
 def prism_probe_diffraction(d: prism_smatrix_desc, S, plan: ProbePlan, precision: int = PRISM_FP32, ws=None,
                             out=None):
     """out [n_probes, m, m] float32 on the device: |FFT_M(psi_p)|^2 / M^4 (4D output)."""

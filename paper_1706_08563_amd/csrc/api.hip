@@ -377,6 +377,36 @@ int check_desc(const prism_smatrix_desc* d) {
 
 }  // namespace
 
+// ------------------------------------------ fixed scratch (no allocation) --
+// Workspace of prism_probe_outputs_noalloc: one array per GPU, part of the
+// code object, held until the process ends.  Host code takes its device
+// address from hipGetSymbolAddress (once per device, with that device
+// current) and never uses the array's name, which on the host is only a
+// stand-in for the symbol.
+static __device__ __align__(256) char scratch[PRISM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+int scratch_address(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PRISM_E_DEVICE, "device index %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PRISM_E_DEVICE, "scratch array has no device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PRISM_OK;
+}
+}  // namespace
+
 // =================================================================== ABI ==
 extern "C" {
 
@@ -906,6 +936,23 @@ int prism_probe_outputs(const prism_smatrix_desc* d, const void* S, const prism_
     if (!ws || ws_bytes < plan->ws_bytes)
         return fail(PRISM_E_WORKSPACE, "probe outputs: workspace %zu < %zu bytes", ws_bytes, plan->ws_bytes);
     if (plan->n_probes == 0) return PRISM_OK;
+    return synth_run(&jb, 1, precision, ws, as_stream(stream));
+}
+
+int prism_probe_outputs_noalloc(const prism_smatrix_desc* d, const void* S, const prism_probe_plan* plan,
+                                const void* plan_dev, int32_t precision, float* out, void* stream) {
+    prism_probe_job jb{d, S, plan, plan_dev, out, nullptr, 1.0f, 0};
+    size_t need = 0;
+    int rc = synth_validate(&jb, 1, precision, &need);
+    if (rc) return rc;
+    const size_t want = std::max(need, plan->ws_bytes);
+    if (want > (size_t)PRISM_NOALLOC_SCRATCH_BYTES)
+        return fail(PRISM_E_WORKSPACE, "probe outputs (no allocation): %zu bytes of workspace needed, the fixed scratch holds %zu",
+                    want, (size_t)PRISM_NOALLOC_SCRATCH_BYTES);
+    if (plan->n_probes == 0) return PRISM_OK;
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
     return synth_run(&jb, 1, precision, ws, as_stream(stream));
 }
 
