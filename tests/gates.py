@@ -33,12 +33,18 @@ def per_bin_max(got, ref):
 
 
 def check_D(got, ref, label, tol=TOL, adf_from=0.04, dalpha=1e-3):
-    """Gate (tol not None) or only report (tol None) a 3D output against its reference."""
+    """Gate (tol not None) or only report (tol None) a 3D output against its
+    reference.  adf_from=None: the outputs are not annular bins (virtual
+    detectors), so there is no dark-field signal to gate."""
     got = np.atleast_2d(np.asarray(got, dtype=np.float64))
     ref = np.atleast_2d(np.asarray(ref, dtype=np.float64))
     assert got.shape == ref.shape, (got.shape, ref.shape)
     e_all = O.rel_err(got, ref)
-    e_adf = O.rel_err(O.adf_signal(got, dalpha, adf_from), O.adf_signal(ref, dalpha, adf_from))
+    if adf_from is None:
+        e_adf = 0.0
+    else:
+        assert ref.shape[1] * dalpha > adf_from, (label, "no bin reaches the dark-field range")
+        e_adf = O.rel_err(O.adf_signal(got, dalpha, adf_from), O.adf_signal(ref, dalpha, adf_from))
     pb = per_bin_max(got, ref)
     worst = np.argsort(pb)[::-1][:3]
     say(f"  {label}: rel_all={e_all:.3e} rel_adf={e_adf:.3e} per-bin max={pb.max():.3e} "

@@ -116,3 +116,51 @@ def test_full_multislice_sampled_probes(P):
     lam, sig = O.wavelength(w.E0), O.interaction_constant(w.E0)
     ref = O.multislice_outputs(Vref, w.cell[0], w.dz, lam, sig, w.alpha_max, xy[pick])
     check_D(out[pick], ref, "multislice sampled probes")
+
+
+def _fixture(name):
+    """FP64 3D outputs of a workload's 16 x 16 probe subset, written by
+    tests/golden/make_golden.py from the oracle alone."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_fp64_subset.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{os.path.basename(path)} not written (tests/golden/make_golden.py --workload {name})")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+@pytest.mark.parametrize("cfg", ["prism_f4_np_1024", "prism_f8_np_2048"])
+def test_end_to_end_against_fp64_fixture(P, cfg):
+    """The benchmarked path end to end: the GPU-built S-matrix of every beam of
+    the aperture through every slice, synthesised at the 16 x 16 probe subset
+    of the full scan in the same plan as the whole scan (so the subset's
+    windows come from the launch the benchmark times), against the FP64
+    oracle's streamed PRISM of the same cell; multislice on the same probes
+    for the 1024^2 cell.  FP32 and split-BF16 are gated, plain BF16 reported."""
+    import torch
+    w = W.WORKLOADS[cfg]
+    fx = _fixture(cfg)
+    say(f"end to end {cfg}: GPU S-matrix + full-scan synthesis vs FP64 fixture ({len(fx['probe_xy'])} probes)")
+    pos, sp = W.atoms_for(w)
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    V = P.prism_project_potential(pos, sp, w.species, g)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    assert np.array_equal(P.prism_beam_list(d), fx["beams"])
+    S = P.prism_build_smatrix(d, V)
+    xy = W.scan_positions(w.cell, *w.scan)
+    sub = w.scan[0] // 16
+    j, i = np.meshgrid(np.arange(0, w.scan[1], sub), np.arange(0, w.scan[0], sub), indexing="ij")
+    idx = (j * w.scan[0] + i).ravel()
+    assert np.array_equal(xy[idx], fx["probe_xy"])
+    plan = P.prism_probe_plan_upload(d, xy)
+    for name, prec, tol in (("bf16x3", P.PRISM_SPLIT_BF16X3, TOL), ("fp32", P.PRISM_FP32, TOL),
+                            ("bf16", P.PRISM_BF16, None)):
+        out = P.prism_probe_outputs(d, S, plan, prec)
+        torch.cuda.synchronize()
+        check_D(out[torch.from_numpy(idx).cuda()].cpu().numpy(), fx["prism"], f"{name} PRISM f={w.f}", tol=tol)
+        del out
+    if "multislice" in fx:
+        ms = P.multislice_outputs(g, w.E0, w.alpha_max, V, fx["probe_xy"], batch=256).cpu().numpy()
+        check_D(ms, fx["multislice"], "multislice")
+        # the method's own approximation at this f (GPU and FP64): reported only
+        check_D(fx["prism"], fx["multislice"], f"FP64 PRISM f={w.f} vs FP64 multislice", tol=None)

@@ -567,11 +567,11 @@ def test_plan_upload_rejects_other_probes(P):
     import torch
     g = P.prism_grid_init((32.0, 32.0, 4.0), 2.0, 256)
     d = P.prism_smatrix_plan(g, 80e3, 0.02, 4)
-    a = np.array([[1.0, 1.0], [1.0, 1.0]])          # both windows on the same 9 tiles
-    b = np.array([[1.0, 1.0], [17.0, 17.0]])        # windows on disjoint tiles
+    a = np.array([[1.0, 1.0], [1.0, 1.0]])          # both windows on the same 4 work tiles
+    b = np.array([[1.0, 1.0], [17.0, 17.0]])        # windows on disjoint work tiles
     pa = P.prism_probe_plan_init(d, a)
     pb = P.prism_probe_plan_init(d, b)
-    assert pa.n_entries == pb.n_entries and pa.n_binned == pb.n_binned and pa.plan_bytes == pb.plan_bytes
+    assert pa.n_entries == pb.n_entries and pa.n_binned == pb.n_binned
     assert (pa.max_per_tile, pb.max_per_tile) == (2, 1)
     dev = torch.empty(pb.plan_bytes, dtype=torch.uint8, device="cuda")
     ax = np.ascontiguousarray(a)
@@ -612,8 +612,8 @@ def test_virtual_detectors_prism_and_multislice(P, prec):
     Sref = O.build_smatrix(Vref, L, w.dz, lam, sig, beams)
     ref = O.prism_outputs(Sref, beams, L, w.n, lam, w.f, xy, detector_map=wmap, n_bins=nb)
     mref = O.multislice_outputs(Vref, L, w.dz, lam, sig, w.alpha_max, xy, detector_map=nmap, n_bins=nbm)
-    check_D(out.cpu().numpy(), ref, "segmented PRISM")
-    check_D(ms.cpu().numpy(), mref, "segmented multislice")
+    check_D(out.cpu().numpy(), ref, "segmented PRISM", adf_from=None)
+    check_D(ms.cpu().numpy(), mref, "segmented multislice", adf_from=None)
     # the map is not annular: the quadrants of a ring differ for an off-axis probe
     got = out.cpu().numpy()
     assert np.max(np.abs(got[:, 4] - got[:, 5])) > 1e-6
