@@ -193,8 +193,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--loads", default="0.4,0.8,1.6",
                     help="offered loads, as fractions of the capacity measured by a saturation run")
-    ap.add_argument("--grids", default="256,512,1024",
-                    help="grid sizes of the serving requests (2048 adds builds of tens of seconds)")
+    ap.add_argument("--grids", default="256,512,1024,2048", help="grid sizes of the serving requests")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave the bounded serving leg (16 requests, one offered load) out of the default run")
     ap.add_argument("--precision-study", action="store_true",
                     help="only the 2048^2 f=8 contraction precision study (part of the default run)")
     ap.add_argument("--no-precision-study", action="store_true",
@@ -264,8 +265,12 @@ def cpu_model():
     return None
 
 
-def run_serving(args):
-    """Continuous-batching serving of a Poisson stream of mixed PRISM requests."""
+def serving_report(args, n_requests, grids, loads, seed=4, quiet=False):
+    """Continuous-batching serving of a Poisson stream of mixed PRISM requests
+    (`n_requests` requests of the stream seeded `seed`): a saturation run for
+    the capacity, then one run per offered load (fraction of that capacity),
+    alone-vs-mix for the three smallest requests and a sequential plain
+    multislice baseline on the same GPU.  Returns the report."""
     import numpy as np
     import torch
 
@@ -274,8 +279,6 @@ def run_serving(args):
     import workloads as W
 
     prec = {"fp32": P.PRISM_FP32, "bf16x3": P.PRISM_SPLIT_BF16X3, "bf16": P.PRISM_BF16}[args.precision]
-    grids = tuple(int(x) for x in args.grids.split(","))
-    loads = [float(x) for x in args.loads.split(",")]
     free, total = torch.cuda.mem_get_info()
     cap = int(0.8 * free)
 
@@ -283,7 +286,7 @@ def run_serving(args):
         """The request stream (same requests, arrivals scaled to `rate`)
         through a fresh scheduler and executor; returns (scheduler, wall s)."""
         reqs = []
-        for p in W.serving_stream(args.requests, rate, grids=grids):
+        for p in W.serving_stream(n_requests, rate, seed=seed, grids=grids):
             r = SV.Request(**p)
             r.sample = W.serving_sample(r.cell, r.seed)
             reqs.append(r)
@@ -291,8 +294,9 @@ def run_serving(args):
         ex = SV.GpuExecutor(prec, jobs_per_request=4)
         sched = SV.Scheduler(cap, max_building=4, max_jobs=24, jobs_per_request=4)
         t0 = time.perf_counter()
-        SV.serve(reqs, ex, sched, on_done=lambda r: log(f"  [{tag}] done {r.rid} n={r.n} f={r.f} S={r.n_slices} "
-                                                        f"P={r.n_probes} latency {r.latency:.2f} s"))
+        SV.serve(reqs, ex, sched, on_done=None if quiet else
+                 lambda r: log(f"  [{tag}] done {r.rid} n={r.n} f={r.f} S={r.n_slices} P={r.n_probes} "
+                               f"latency {r.latency:.2f} s"))
         torch.cuda.synchronize()
         return sched, time.perf_counter() - t0
 
@@ -336,11 +340,13 @@ def run_serving(args):
     res = {"metric": "serving: aggregate probe positions/s, p50/p99 latency (mixed PRISM requests)",
            "value": summ["probes_per_s"], "unit": "probe positions/s", "n_gpus": 1,
            "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+           "latency_by_grid": summ["latency_by_grid"], "stream_seed": seed,
            "requests": summ["requests"], "rejected": summ["rejected"], "probes": summ["probes"],
            "wall_s": wall, "arrival_rate_per_s": rate, "offered_load": ld0,
            "capacity_requests_per_s": capacity, "saturation_probes_per_s": SV.summarize(sat, sat_wall)["probes_per_s"],
            "load_sweep": {str(k): {"probes_per_s": v[2]["probes_per_s"], "p50_latency_s": v[2]["p50_latency_s"],
-                                   "p99_latency_s": v[2]["p99_latency_s"], "wall_s": v[1]}
+                                   "p99_latency_s": v[2]["p99_latency_s"], "wall_s": v[1],
+                                   "latency_by_grid": v[2]["latency_by_grid"]}
                           for k, v in sweep.items()},
            "hbm_budget_GB": cap / 1e9, "peak_reserved_GB": summ["peak_hbm_reserved"] / 1e9,
            "precision": args.precision, "grids": list(grids),
@@ -350,7 +356,14 @@ def run_serving(args):
            "sequential_multislice_s_extrapolated": ms_time,
            "speedup_vs_sequential_multislice": ms_time / wall if wall > 0 else None,
            "data": "synthetic"}
-    print(json.dumps(res), flush=True)
+    return res
+
+
+def run_serving(args):
+    """The serving benchmark alone (`--serve`)."""
+    grids = tuple(int(x) for x in args.grids.split(","))
+    loads = [float(x) for x in args.loads.split(",")]
+    print(json.dumps(serving_report(args, args.requests, grids, loads)), flush=True)
 
 
 def multislice_leg(args):
@@ -719,6 +732,13 @@ def main():
         del S, ws_build, ws_probe, out, V
         torch.cuda.empty_cache()
         res["precision_study"] = precision_study(args)
+    if not args.no_serving:
+        # bounded serving leg: 16 requests of the serving distribution (all
+        # four grid sizes; the stream seeded 40 holds one 2048^2 f = 2
+        # request of 19973 beams among small ones), offered load 0.8
+        log("serving leg (16 requests, load 0.8)")
+        torch.cuda.empty_cache()
+        res["serving"] = serving_report(args, 16, (256, 512, 1024, 2048), [0.8], seed=40, quiet=True)
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle, bounded sample)")
         res["cpu_baseline"] = cpu_baseline(w, d, B, n_probes, args)

@@ -111,15 +111,16 @@ typedef struct prism_aberrations {
 typedef struct prism_probe_plan {
     int64_t n_probes;
     int32_t n_bins;          /* detector bins (3D output depth) */
-    int32_t n_tiles;         /* S-grid pixel tiles touched by at least one window */
-    int64_t n_entries;       /* (tile, probe) pairs */
-    int32_t max_per_tile;    /* largest probe count of one tile */
+    int32_t n_tiles;         /* work tiles of the contraction: (tiling phase, 16 x 16 S-grid
+                                pixel tile) pairs that at least one window overlaps */
+    int64_t n_entries;       /* (work tile, probe) pairs */
+    int32_t max_per_tile;    /* largest probe count of one work tile */
     int32_t n_binned;        /* window pixels that fall in a detector bin */
     double dalpha;           /* bin width (rad) */
     size_t plan_bytes;       /* device bytes of the plan tables */
     size_t ws_bytes;         /* workspace of prism_probe_outputs for all probes at once */
     double C1, C3;           /* aberrations the plan was made with */
-    size_t off[9];           /* internal: offsets of the tables inside the plan buffer */
+    size_t off[10];          /* internal: offsets of the tables inside the plan buffer */
 } prism_probe_plan;
 
 /* ---- grid ---------------------------------------------------------------- */
@@ -168,6 +169,18 @@ int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap);
  * PRISM_E_DEVICE. */
 int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S,
                         void* ws, size_t ws_bytes, void* stream);
+
+/* Layers first .. first + count - 1 of the S-matrix of prism_build_smatrix
+ * (beams in the order of prism_beam_list), bit-identical to the same layers
+ * of the whole build; the other layers of S are not written.  S is the
+ * whole S-matrix (n_beams layers).  For callers that issue a large build in
+ * parts, e.g. a serving loop that keeps other requests' work from queuing
+ * behind all of it.  Same workspace as prism_build_smatrix (sized by
+ * beam_batch, not by count).  Uploads host tables.
+ * Errors: as prism_build_smatrix; PRISM_E_INVAL when the range is not inside
+ * [0, n_beams). */
+int prism_build_smatrix_range(const prism_smatrix_desc* d, const float* V, void* S, int32_t first,
+                              int32_t count, void* ws, size_t ws_bytes, void* stream);
 
 /* Streams used by prism_build_smatrix (process-wide), n in 1..4 (default 2):
  * every beam batch is split into n parts, run on `stream` and on n - 1
@@ -433,7 +446,7 @@ int prism_detector_default_bins(const prism_grid* grid, double E0, double dalpha
 #define PRISM_K_WINDOW         6   /* window FFT, |Psi|^2, detector sums */
 #define PRISM_K_POTENTIAL      7   /* projected potential */
 #define PRISM_K_BIN_REDUCE     8   /* multislice detector sums */
-#define PRISM_K_SPLIT          9   /* S-matrix to split-BF16 tile records (MFMA precisions) */
+#define PRISM_K_SPLIT          9   /* S-matrix to split-BF16 records (MFMA precisions) */
 #define PRISM_TIMING_CLASSES  10
 
 /* While enabled (per calling thread), every kernel launch of the library is

@@ -12,7 +12,7 @@ from ._lib import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     lib, prism_grid_init, prism_smatrix_plan, prism_beam_list, prism_detector_bin_map, prism_detector_default_bins,
-    prism_project_potential, prism_build_smatrix, prism_probe_plan_init, prism_probe_plan_upload,
+    prism_project_potential, prism_build_smatrix, prism_build_smatrix_range, prism_probe_plan_init, prism_probe_plan_upload,
     prism_probe_outputs, multislice_outputs, multislice_workspace, ProbePlan,
     prism_timing_enable, prism_timing_reset, prism_timing_read,
     prism_probe_batch_workspace, prism_probe_outputs_batched, prism_probe_diffraction,

@@ -52,7 +52,7 @@ class prism_probe_plan(ctypes.Structure):
     _fields_ = [("n_probes", c_int64), ("n_bins", c_int32), ("n_tiles", c_int32), ("n_entries", c_int64),
                 ("max_per_tile", c_int32), ("n_binned", c_int32), ("dalpha", c_double),
                 ("plan_bytes", c_size_t), ("ws_bytes", c_size_t), ("C1", c_double), ("C3", c_double),
-                ("off", c_size_t * 9)]
+                ("off", c_size_t * 10)]
 
 
 class prism_probe_job(ctypes.Structure):
@@ -77,6 +77,8 @@ _SIGNATURES = {
     "prism_beam_list": ([POINTER(prism_smatrix_desc), c_void_p, c_int32], c_int32),
     "prism_build_smatrix": ([POINTER(prism_smatrix_desc), c_void_p, c_void_p, c_void_p, c_size_t, c_void_p],
                             c_int32),
+    "prism_build_smatrix_range": ([POINTER(prism_smatrix_desc), c_void_p, c_void_p, c_int32, c_int32, c_void_p,
+                                   c_size_t, c_void_p], c_int32),
     "prism_probe_plan_init": ([POINTER(prism_smatrix_desc), c_void_p, c_int64, c_double, c_int32,
                                POINTER(prism_aberrations), POINTER(prism_probe_plan)], c_int32),
     "prism_probe_plan_upload": ([POINTER(prism_smatrix_desc), c_void_p, POINTER(prism_probe_plan), c_void_p,

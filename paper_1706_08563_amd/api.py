@@ -113,6 +113,15 @@ def prism_build_smatrix(d: prism_smatrix_desc, V, ws=None, S=None):
     return S
 
 
+def prism_build_smatrix_range(d: prism_smatrix_desc, V, S, first: int, count: int, ws=None):
+    """Layers first .. first + count - 1 of S (the whole [n_beams, n/2, n/2] array)."""
+    if ws is None:
+        ws = _workspace(d.build_ws_bytes, V.device)
+    check(lib.prism_build_smatrix_range(ctypes.byref(d), _dev(V), _dev(S), int(first), int(count), _dev(ws),
+                                        ws.numel(), _stream()))
+    return S
+
+
 # -------------------------------------------------------- probe outputs --
 @dataclass
 class ProbePlan:

@@ -111,10 +111,13 @@ inline int bin_of(double lam, int kx, int ky, double Lw, double a_aa, double dal
 }
 
 // Beams: every f-th Fourier index inside alpha_max, ordered by (ky, kx).
+// Indices beyond kmax = alpha_max L / lam (+1 for rounding) per axis are
+// outside the aperture, so the scan is limited to that square.
 std::vector<int2> beam_list(int n, double L, double lam, double alpha_max, int f) {
     std::vector<int2> out;
-    for (int ky = -n / 2; ky < n / 2; ++ky)
-        for (int kx = -n / 2; kx < n / 2; ++kx) {
+    const int kmax = (int)std::min<double>(n / 2, std::ceil(alpha_max * L / lam) + 1.0);
+    for (int ky = std::max(-n / 2, -kmax); ky < std::min(n / 2, kmax + 1); ++ky)
+        for (int kx = std::max(-n / 2, -kmax); kx < std::min(n / 2, kmax + 1); ++kx) {
             if (kx % f != 0 || ky % f != 0) continue;
             if (angle_of(lam, kx, ky, L) <= alpha_max) out.push_back(make_int2(kx, ky));
         }
@@ -239,6 +242,7 @@ struct ProbeHost {
     std::vector<double2> xy;
     std::vector<int2> corner;
     std::vector<int> tile_start, tile_probes, perm, bin_start;
+    std::vector<int2> tile_origin;  // first pixel of each work tile
     std::vector<float2> tw_m;
     std::vector<int2> beams;
     std::vector<float2> aberr;      // per beam, empty when there are no aberrations
@@ -281,48 +285,104 @@ int check_detector_map(const int32_t* dmap, size_t count, int n_bins, const char
     return PRISM_OK;
 }
 
+// Work tiles of the windowed contraction.  Each probe gets a tiling phase,
+// its window corner's offset modulo 16 rounded down to a multiple of the
+// quantum Q (Q = 16: one phase for all probes; Q = 1: the exact offset, so
+// that the window covers whole tiles), and is listed under every 16 x 16
+// tile of its phase that its window overlaps.  A work tile is a (phase,
+// tile) pair with at least one probe.
+struct TileCover {
+    int nt, nq, Q, M, ns;
+    // tiles of the phase grid covered along one axis by a window starting at c
+    void span(int c, int& phase, int& first, int& count) const {
+        phase = (c & 15) / Q;
+        const int rel = (c - phase * Q) & (ns - 1);
+        first = rel / 16;
+        count = std::min((rel + M - 1) / 16 - first + 1, nt);   // a window as wide as the grid covers each tile once
+    }
+    int key(int phx, int phy, int tx, int ty) const { return ((phy * nq + phx) * nt + ty) * nt + tx; }
+};
+
+// Probe count of every (phase, tile) key for quantum Q.
+static void cover_counts(const TileCover& tc, const std::vector<int2>& corner, std::vector<int>& count) {
+    count.assign((size_t)tc.nq * tc.nq * tc.nt * tc.nt, 0);
+    for (const int2& c : corner) {
+        int px, fx, nx, py, fy, ny;
+        tc.span(c.x, px, fx, nx);
+        tc.span(c.y, py, fy, ny);
+        for (int a = 0; a < ny; ++a)
+            for (int b = 0; b < nx; ++b) count[tc.key(px, py, (fx + b) % tc.nt, (fy + a) % tc.nt)]++;
+    }
+}
+
+// Interleaved bits of (ty, tx): work tiles near each other in the S grid get
+// nearby places in the launch order.
+static uint32_t morton(uint32_t ty, uint32_t tx) {
+    uint32_t r = 0;
+    for (int b = 0; b < 16; ++b) r |= ((tx >> b) & 1u) << (2 * b) | ((ty >> b) & 1u) << (2 * b + 1);
+    return r;
+}
+
 int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, double dalpha, int n_bins,
                double C1, double C3, const int32_t* dmap, ProbeHost& h, int& max_per_tile) {
     const int n = d->grid.n, ns = d->ns, M = d->m_win;
     const double L = d->grid.cell[0];
-    const int ntx = ns / 16, n_tiles = ntx * ntx;
     h.xy.resize(n_probes);
     h.corner.resize(n_probes);
-    std::vector<int> count(n_tiles, 0);
-    std::vector<char> mark_x(ntx), mark_y(ntx);
-    auto cover = [&](int start, std::vector<char>& mark) {
-        std::fill(mark.begin(), mark.end(), 0);
-        for (int v = 0; v < M; v += 16) mark[((start + v) & (ns - 1)) / 16] = 1;
-        mark[((start + M - 1) & (ns - 1)) / 16] = 1;
-    };
     for (int64_t p = 0; p < n_probes; ++p) {
         double x = xy[2 * p], y = xy[2 * p + 1];
         if (!std::isfinite(x) || !std::isfinite(y)) return fail(PRISM_E_INVAL, "probe %lld: non-finite position", (long long)p);
         h.xy[p] = make_double2(x, y);
         int cx = centre_of(x, L, n), cy = centre_of(y, L, n);
         h.corner[p] = make_int2((cx - M / 2) & (ns - 1), (cy - M / 2) & (ns - 1));
-        cover(h.corner[p].x, mark_x);
-        cover(h.corner[p].y, mark_y);
-        for (int ty = 0; ty < ntx; ++ty)
-            if (mark_y[ty])
-                for (int tx = 0; tx < ntx; ++tx)
-                    if (mark_x[tx]) count[ty * ntx + tx]++;
     }
+    // the quantum whose work tiles need the fewest workgroups of the MFMA
+    // contraction's probe chunk (ties: the coarser tiling)
+    const int pc = contract_probe_chunk();
+    TileCover tc{ns / 16, 1, 16, M, ns};
+    std::vector<int> count;
+    long long best = -1;
+    for (int Q : {16, 1}) {
+        TileCover t{ns / 16, 16 / Q, Q, M, ns};
+        cover_counts(t, h.corner, count);
+        long long cost = 0;
+        for (int c : count) cost += (c + pc - 1) / pc;
+        if (best < 0 || cost < best) {
+            best = cost;
+            tc = t;
+        }
+    }
+    cover_counts(tc, h.corner, count);
+    std::vector<std::pair<uint64_t, int>> order;   // (position, phase) sort key, key
+    for (int k = 0; k < (int)count.size(); ++k) {
+        if (!count[k]) continue;
+        const int tx = k % tc.nt, ty = (k / tc.nt) % tc.nt, ph = k / (tc.nt * tc.nt);
+        order.emplace_back(((uint64_t)morton(ty, tx) << 16) | (uint64_t)ph, k);
+    }
+    std::sort(order.begin(), order.end());
+    std::vector<int> slot(count.size(), -1);
+    const int n_tiles = (int)order.size();
     h.tile_start.assign(n_tiles + 1, 0);
+    h.tile_origin.resize(n_tiles);
     max_per_tile = 0;
     for (int t = 0; t < n_tiles; ++t) {
-        h.tile_start[t + 1] = h.tile_start[t] + count[t];
-        max_per_tile = std::max(max_per_tile, count[t]);
+        const int k = order[t].second;
+        const int tx = k % tc.nt, ty = (k / tc.nt) % tc.nt, ph = k / (tc.nt * tc.nt);
+        const int phx = ph % tc.nq, phy = ph / tc.nq;
+        slot[k] = t;
+        h.tile_start[t + 1] = h.tile_start[t] + count[k];
+        h.tile_origin[t] = make_int2((phx * tc.Q + 16 * tx) & (ns - 1), (phy * tc.Q + 16 * ty) & (ns - 1));
+        max_per_tile = std::max(max_per_tile, count[k]);
     }
     h.tile_probes.assign(h.tile_start[n_tiles], 0);
     std::vector<int> fill(h.tile_start.begin(), h.tile_start.end() - 1);
     for (int64_t p = 0; p < n_probes; ++p) {
-        cover(h.corner[p].x, mark_x);
-        cover(h.corner[p].y, mark_y);
-        for (int ty = 0; ty < ntx; ++ty)
-            if (mark_y[ty])
-                for (int tx = 0; tx < ntx; ++tx)
-                    if (mark_x[tx]) h.tile_probes[fill[ty * ntx + tx]++] = (int)p;
+        int px, fx, nx, py, fy, ny;
+        tc.span(h.corner[p].x, px, fx, nx);
+        tc.span(h.corner[p].y, py, fy, ny);
+        for (int a = 0; a < ny; ++a)
+            for (int b = 0; b < nx; ++b)
+                h.tile_probes[fill[slot[tc.key(px, py, (fx + b) % tc.nt, (fy + a) % tc.nt)]]++] = (int)p;
     }
     bin_tables(d->lambda, L / d->f, d->alpha_aa, dalpha, n_bins, M, dmap, h.perm, h.bin_start);
     h.tw_m = twiddle_table(M);
@@ -356,9 +416,11 @@ SynthJobDev synth_job_carve(const prism_smatrix_desc* d, const prism_probe_plan*
     j.inten = d->m_win > 128 ? c.take<float>(P * d->m_win * d->m_win) : nullptr;
     return j;
 }
-// The MFMA contraction reads S in its split layout, converted once per
-// distinct S-matrix of a call.
-void* split_s_carve(const prism_smatrix_desc* d, Carve& c) { return c.take<char>(split_s_bytes(d->ns, d->n_beams)); }
+// The MFMA contraction reads S as split records, converted once per distinct
+// S-matrix of a call (nothing is reserved when it splits S itself).
+void* split_s_carve(const prism_smatrix_desc* d, Carve& c) {
+    return contract_reads_split_s() ? c.take<char>(split_s_bytes(d->ns, d->n_beams)) : nullptr;
+}
 
 // Consistency of a descriptor filled by prism_smatrix_plan (without recounting
 // the beams, which costs O(n^2) host work per call).
@@ -618,14 +680,20 @@ int prism_set_build_streams(int32_t n) {
     return PRISM_OK;
 }
 
-int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, void* ws, size_t ws_bytes,
-                        void* stream) {
+// S-matrix layers [first, first + count): all slices of each beam batch,
+// then the real-space store.
+static int build_range(const prism_smatrix_desc* d, const float* V, void* S, int first, int count, void* ws,
+                       size_t ws_bytes, void* stream) {
     int rc = check_desc(d);
     if (rc) return rc;
     if (!V || !S) return fail(PRISM_E_INVAL, "build: NULL V or S");
+    if (first < 0 || count < 0 || first > d->n_beams - count)
+        return fail(PRISM_E_INVAL, "build: beam range [%d, %d + %d) outside [0, %d)", first, first, count, d->n_beams);
     if (!ws || ws_bytes < d->build_ws_bytes)
         return fail(PRISM_E_WORKSPACE, "build: workspace %zu < %zu bytes", ws_bytes, d->build_ws_bytes);
-    const int n = d->grid.n, B = d->n_beams, nsl = d->grid.n_slices, NB = batch_of(d);
+    if (count == 0) return PRISM_OK;
+    const int n = d->grid.n, B = d->n_beams, nsl = d->grid.n_slices, NB = std::min(batch_of(d), count);
+    const int end = first + count;
     const double L = d->grid.cell[0];
     hipStream_t st = as_stream(stream);
     Carve c(ws);
@@ -671,8 +739,8 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
         if (got < P - 1) P = 1;
     }
     if (P <= 1) {
-        for (int b0 = 0; b0 < B; b0 += NB) {
-            rc = run_items(b0, 0, std::min(NB, B - b0), st, nullptr);
+        for (int b0 = first; b0 < end; b0 += NB) {
+            rc = run_items(b0, 0, std::min(NB, end - b0), st, nullptr);
             if (rc) return rc;
         }
         return PRISM_OK;
@@ -687,18 +755,18 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
     auto off = [&](int k) { return (int)((int64_t)k * NB / P); };
     int forked = 1;                              // streams that may hold work of this call
     auto enqueue = [&]() -> int {
-        for (int b0 = 0; b0 < B; b0 += NB) {
-            const int nb = std::min(NB, B - b0);
+        for (int b0 = first; b0 < end; b0 += NB) {
+            const int nb = std::min(NB, end - b0);
             for (int k = 0; k < P; ++k) {
                 const int i0 = off(k), cnt = std::min(off(k + 1), nb) - i0;
-                if (b0 == 0 && k > 0) {
+                if (b0 == first && k > 0) {
                     HIP_TRY(hipStreamWaitEvent(q[k], be.ev[k - 1], 0));
                     forked = k + 1;
                 }
                 if (cnt > 0) {
-                    int r = run_items(b0, i0, cnt, q[k], b0 == 0 ? be.ev[k] : nullptr);
+                    int r = run_items(b0, i0, cnt, q[k], b0 == first ? be.ev[k] : nullptr);
                     if (r) return r;
-                } else if (b0 == 0) {
+                } else if (b0 == first) {
                     HIP_TRY(hipEventRecord(be.ev[k], q[k]));
                 }
             }
@@ -714,6 +782,18 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, vo
         if (e != hipSuccess && rc == PRISM_OK) rc = fail(PRISM_E_DEVICE, "build: stream join: %s", hipGetErrorString(e));
     }
     return rc;
+}
+
+int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S, void* ws, size_t ws_bytes,
+                        void* stream) {
+    if (!d) return fail(PRISM_E_INVAL, "descriptor is NULL");
+    return build_range(d, V, S, 0, d->n_beams, ws, ws_bytes, stream);
+}
+
+int prism_build_smatrix_range(const prism_smatrix_desc* d, const float* V, void* S, int32_t first, int32_t count,
+                              void* ws, size_t ws_bytes, void* stream) {
+    if (!d) return fail(PRISM_E_INVAL, "descriptor is NULL");
+    return build_range(d, V, S, first, count, ws, ws_bytes, stream);
 }
 
 // -------------------------------------------------------- probe outputs --
@@ -759,6 +839,7 @@ static int probe_plan_make(const prism_smatrix_desc* d, const double* probe_xy, 
     p.off[6] = (size_t)c.take<float2>(h.tw_m.size());
     p.off[7] = (size_t)c.take<int2>(h.beams.size());
     p.off[8] = h.aberr.empty() ? 0 : (size_t)c.take<float2>(h.aberr.size());
+    p.off[9] = (size_t)c.take<int2>(std::max<size_t>(h.tile_origin.size(), 1));
     p.plan_bytes = c.off + 256;
     Carve w(nullptr);
     synth_job_carve(d, &p, w);
@@ -814,6 +895,7 @@ static int probe_plan_put(const prism_smatrix_desc* d, const double* probe_xy, c
     put(plan->off[6], h.tw_m.data(), h.tw_m.size() * sizeof(float2));
     put(plan->off[7], h.beams.data(), h.beams.size() * sizeof(int2));
     if (!h.aberr.empty()) put(plan->off[8], h.aberr.data(), h.aberr.size() * sizeof(float2));
+    put(plan->off[9], h.tile_origin.data(), h.tile_origin.size() * sizeof(int2));
     return upload(plan_dev, blob, as_stream(stream));
 }
 
@@ -865,6 +947,7 @@ static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, voi
     std::vector<ContractArgs> ca;
     std::vector<std::vector<WindowArgs>> wa(10);   // by log2(m)
     const bool split = precision != PRISM_FP32;
+    const bool split_s = split && contract_reads_split_s();
     Carve c(ws);
     std::vector<SynthJobDev> jd(n_jobs);
     for (int k = 0; k < n_jobs; ++k) jd[k] = synth_job_carve(jobs[k].desc, jobs[k].plan, c);
@@ -876,13 +959,13 @@ static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, voi
             continue;
         }
         void* ss = split_s_carve(jobs[k].desc, c);
-        s_op[k] = split ? ss : jobs[k].S;
+        s_op[k] = split_s ? ss : jobs[k].S;
         // the split copy serves every job on this S-matrix: convert it when
         // any of them has probes (the first may have none)
         bool used = false;
         for (int i = k; i < n_jobs && !used; ++i)
             used = jobs[i].plan->n_probes > 0 && first_with_same_s(jobs, i) == k;
-        if (split && used) {
+        if (split_s && used) {
             const prism_smatrix_desc* d = jobs[k].desc;
             HIP_TRY(timed(PRISM_K_SPLIT, st, [&] {
                 return launch_split_s(precision, static_cast<const float2*>(jobs[k].S), ss, d->n_beams, d->ns, st);
@@ -905,13 +988,14 @@ static int synth_run(const prism_probe_job* jobs, int n_jobs, int precision, voi
         auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
         auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
         auto aberr = (plan->C1 != 0.0 || plan->C3 != 0.0) ? reinterpret_cast<const float2*>(pb + plan->off[8]) : nullptr;
+        auto torigin = reinterpret_cast<const int2*>(pb + plan->off[9]);
         const double inv_L = 1.0 / d->grid.cell[0];
         const float amp = (float)(1.0 / std::sqrt((double)B));
         HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
             return split ? launch_coefficients_split(precision, jd[k].C, xy, beams, aberr, P, B, inv_L, amp, st)
                          : launch_coefficients(static_cast<float2*>(jd[k].C), xy, beams, aberr, P, B, inv_L, amp, st);
         }));
-        ca.push_back(ContractArgs{jd[k].C, s_op[k], jd[k].win, tstart, tprobes, corner, plan->n_tiles,
+        ca.push_back(ContractArgs{jd[k].C, s_op[k], jd[k].win, tstart, tprobes, torigin, corner, plan->n_tiles,
                                   plan->max_per_tile, B, d->ns, M});
         int lg = 0;
         while ((1 << lg) < M) ++lg;
@@ -1368,7 +1452,7 @@ static void stream_synth_carve(Carve& c, const prism_smatrix_desc* d, const pris
     m.Sst[0] = slots ? c.take<float2>((size_t)chunk * d->ns * d->ns) : nullptr;
     m.Sst[1] = slots ? c.take<float2>((size_t)chunk * d->ns * d->ns) : nullptr;
     m.C = c.take<char>(split_c_bytes((int64_t)P, chunk));
-    m.Ssplit = c.take<char>(split_s_bytes(d->ns, chunk));
+    m.Ssplit = contract_reads_split_s() ? c.take<char>(split_s_bytes(d->ns, chunk)) : nullptr;
     m.win = c.take<float2>(P * M * M);
     m.inten = M > 128 ? c.take<float>(P * M * M) : nullptr;
 }
@@ -1418,6 +1502,7 @@ static int synth_chunked(const prism_smatrix_desc* d, const void* S, const prism
     auto tw_m = reinterpret_cast<const float2*>(pb + plan->off[6]);
     auto beams = reinterpret_cast<const int2*>(pb + plan->off[7]);
     auto aberr = (plan->C1 != 0.0 || plan->C3 != 0.0) ? reinterpret_cast<const float2*>(pb + plan->off[8]) : nullptr;
+    auto torigin = reinterpret_cast<const int2*>(pb + plan->off[9]);
     const float amp = (float)(1.0 / std::sqrt((double)B));
     const bool split = precision != PRISM_FP32;
     const double inv_L = 1.0 / d->grid.cell[0];
@@ -1442,20 +1527,19 @@ static int synth_chunked(const prism_smatrix_desc* d, const void* S, const prism
         }
         const float2* ab = aberr ? aberr + c0 : nullptr;
         const void* s_op = chunk;
-        if (split) {
+        if (split && contract_reads_split_s()) {
             HIP_TRY(timed(PRISM_K_SPLIT, st, [&] { return launch_split_s(precision, chunk, m.Ssplit, nb, d->ns, st); }));
             s_op = m.Ssplit;
         }
-        // a streamed slot is free again once its chunk has been read
-        if (streamed && split) HIP_TRY(hipEventRecord(r.freed[k], st));
         HIP_TRY(timed(PRISM_K_COEFFICIENTS, st, [&] {
             return split ? launch_coefficients_split(precision, m.C, xy, beams + c0, ab, P, nb, inv_L, amp, st)
                          : launch_coefficients(static_cast<float2*>(m.C), xy, beams + c0, ab, P, nb, inv_L, amp, st);
         }));
-        ContractArgs ca{m.C, s_op, m.win, tstart, tprobes, corner, plan->n_tiles, plan->max_per_tile, nb, d->ns, M,
-                        ci > 0 ? 1 : 0};
+        ContractArgs ca{m.C, s_op, m.win, tstart, tprobes, torigin, corner, plan->n_tiles, plan->max_per_tile, nb,
+                        d->ns, M, ci > 0 ? 1 : 0};
         HIP_TRY(timed(PRISM_K_CONTRACT, st, [&] { return launch_contract_batch(precision, &ca, 1, st); }));
-        if (streamed && !split) HIP_TRY(hipEventRecord(r.freed[k], st));
+        // a streamed slot is free again once its chunk has been read
+        if (streamed) HIP_TRY(hipEventRecord(r.freed[k], st));
         if (streamed) r.used[k] = true;
     }
     WindowArgs wa{m.win, m.inten, out, out4d, perm, bstart, tw_m, P, plan->n_bins, 1.0f, 0};

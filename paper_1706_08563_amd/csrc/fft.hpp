@@ -199,6 +199,13 @@ struct FftT {
         float2* p;
         __device__ __forceinline__ float2& operator()(int i) const { return p[pad(i)]; }
     };
+    // The same padded buffer with a compile-time stride between consecutive
+    // slots (a column of a row-major array, exchanged in place).
+    template <int STRIDE>
+    struct StrideX {
+        float2* p;
+        __device__ __forceinline__ float2& operator()(int i) const { return p[pad(i) * STRIDE]; }
+    };
 
     template <int DIR, int S, class X>
     __device__ __forceinline__ static void stage(float2 (&v)[E], const X& lds, const Twiddles& tw, int lt) {
@@ -312,6 +319,11 @@ struct FftT {
     template <int DIR>
     __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, const Twiddles& tw, int lt) {
         stage<DIR, 0>(v, RowX{lds}, tw, lt);
+    }
+    // The same through any exchange accessor (RowX, StrideX).
+    template <int DIR, class X>
+    __device__ __forceinline__ static void run_x(float2 (&v)[E], const X& x, const Twiddles& tw, int lt) {
+        stage<DIR, 0>(v, x, tw, lt);
     }
 };
 

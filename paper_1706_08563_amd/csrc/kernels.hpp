@@ -57,37 +57,45 @@ hipError_t launch_potential(float* V, int n, int n_slices, double L, const PotAt
 hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, const float2* aberr, int n_probes,
                                int n_beams, double inv_L, float amp, hipStream_t st);
 
-// Operand layouts of the MFMA contraction.  A K step is 16 beams; a record
+// Operand records of the MFMA contraction.  A K step is 16 beams; a record
 // holds, for one (pixel or probe, K step), NP parts (hi, lo) x (re, im) x two
 // halves of 8 beams as bf16: NP * 64 bytes, beams past n_beams zero.
-//   split S:  [tile of 16 x 16 pixels][K step][pixel of the tile][record],
-//             16-byte chunks of a record permuted by the pixel (bank spread)
+//   split S:  [K step][pixel y ns + x][record]   (pixel-major)
 //   split C:  [probe][K step][record]
 constexpr int KSTEP = 16;
 inline int ksteps_of(int n_beams) { return (n_beams + KSTEP - 1) / KSTEP; }
 // Bytes reserved for either split layout (the split-BF16 size, the larger).
 inline size_t split_s_bytes(int ns, int n_beams) { return (size_t)ns * ns * ksteps_of(n_beams) * 128; }
 inline size_t split_c_bytes(int64_t n_probes, int n_beams) { return (size_t)n_probes * ksteps_of(n_beams) * 128; }
+// True when the MFMA contraction reads S as split records (launch_split_s
+// first); false when it splits the FP32 S-matrix itself.
+bool contract_reads_split_s();
 // S [n_beams][ns][ns] complex64 -> split S (precision PRISM_SPLIT_BF16X3 or PRISM_BF16).
 hipError_t launch_split_s(int precision, const float2* S, void* Ssplit, int n_beams, int ns, hipStream_t st);
-// Coefficients as launch_coefficients, written as split C.
+// Coefficients as launch_coefficients, written as split C (precision
+// PRISM_SPLIT_BF16X3 or PRISM_BF16).
 hipError_t launch_coefficients_split(int precision, void* Csplit, const double2* xy, const int2* beams,
                                      const float2* aberr, int n_probes, int n_beams, double inv_L, float amp,
                                      hipStream_t st);
 
-// Windowed contraction of one probe set: win[p][v][u] = sum_b C[p][b] S[b][pix].
-// C and S are complex64 ([n_probes][n_beams], [n_beams][ns][ns]) for FP32 and
-// the split layouts above for the MFMA precisions.
+// Windowed contraction of one probe set: win[p][v][u] = sum_b C[p][b] S[b][pix]
+// over the plan's work tiles (16 x 16 pixels from tile_origin, periodic).
+// C and S are complex64 ([n_probes][n_beams], [n_beams][ns][ns]) for FP32;
+// for the MFMA precisions C is split C, and S is split S when
+// contract_reads_split_s() (else complex64).
 struct ContractArgs {
     const void* C;
     const void* S;
     float2* win;
     const int* tile_start;
     const int* tile_probes;
+    const int2* tile_origin;
     const int2* corner;
     int n_tiles, max_per_tile, n_beams, ns, m;
     int accumulate = 0;       // add to the windows (partial sums over beam chunks)
 };
+// Probes per workgroup of the MFMA contraction (the plan's work-tile cost unit).
+int contract_probe_chunk();
 // All jobs in as few launches as possible (one per 24 jobs).
 hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_jobs, hipStream_t st);
 

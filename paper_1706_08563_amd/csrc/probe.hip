@@ -48,12 +48,18 @@ hipError_t launch_coefficients(float2* C, const double2* xy, const int2* beams, 
 }
 
 // --------------------------------------------------- windowed contraction --
-// The S grid is cut into 16 x 16 pixel tiles.  For each tile the plan lists
-// every probe whose M x M window overlaps it.  A workgroup takes one tile and
-// a chunk of PC of those probes and forms, for every tile pixel,
+// The contraction runs over work tiles of 16 x 16 S-grid pixels.  A probe's
+// M x M window starts at its corner; the plan gives every probe a tiling
+// phase (an offset of the 16-pixel tile grid, at most its corner's position
+// modulo 16) and lists the probe under each tile of that phase its window
+// overlaps.  When the phase equals the corner's offset (as for probes on a
+// scan lattice of a few pixels' pitch) the window is exactly (M/16)^2 tiles and
+// no product falls outside it.  A workgroup takes one work tile and a chunk
+// of PC of its probes and forms, for every tile pixel,
 //     acc[p] = sum_b C[p][b] S[b][pixel]
-// then stores each (probe, pixel) that lies inside the probe's window.  Each
-// window element is produced by exactly one (tile, probe) pair, so no atomics.
+// then stores each (probe, pixel) that lies inside the probe's window.  The
+// tiles of one phase partition the S grid, so each window element is
+// produced by exactly one (tile, probe) pair: no atomics.
 constexpr int TILE = 16;
 
 // Work of one (request's) probe synthesis inside a batched contraction launch.
@@ -63,6 +69,7 @@ struct ContractJob {
     float2* win;              // [n_probes][m][m]
     const int* tile_start;    // [n_tiles + 1]
     const int* tile_probes;
+    const int2* tile_origin;  // [n_tiles] first pixel (x, y) of each work tile
     const int2* corner;       // window corner per probe
     int n_beams, ns, m;
     int ksteps;               // K steps of 16 beams (split layouts)
@@ -80,8 +87,9 @@ struct ContractBatch {
 };
 
 // Logical workgroup of this hardware workgroup.  Hardware workgroups are
-// dealt round-robin to the 8 XCDs; logical workgroups l and l+1 are placed on
-// the same XCD, so all probe chunks of a pixel tile share that XCD's L2.
+// dealt round-robin to the 8 XCDs; consecutive logical workgroups are placed
+// on the same XCD, so the probe chunks and phases of neighbouring tiles (the
+// plan orders work tiles by position, then phase) share that XCD's L2.
 // The selected job is copied out by value: taking the address of the
 // by-value kernel argument would force a private-memory copy of the table.
 __device__ __forceinline__ bool locate(const ContractBatch& b, ContractJob& job, int& tile, int& chunk) {
@@ -121,10 +129,10 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
     const int pc0 = t0 + chunk * PC;
     if (pc0 >= t1) return;
     const int np = min(PC, t1 - pc0);
-    const int ntx = ns / TILE;
+    const int2 org = job.tile_origin[tile];
     const int tid = threadIdx.x;
-    const int px = (tile % ntx) * TILE + (tid % TILE);
-    const int py = (tile / ntx) * TILE + (tid / TILE);
+    const int px = (org.x + tid % TILE) & (ns - 1);
+    const int py = (org.y + tid / TILE) & (ns - 1);
     if (tid < PC) pidx[tid] = tid < np ? tile_probes[pc0 + tid] : -1;
     __syncthreads();
 
@@ -182,13 +190,22 @@ __global__ __launch_bounds__(WG) void k_contract_fp32(ContractBatch batch) {
 // and each product is hi*hi + hi*lo + lo*hi accumulated in FP32 (the lo*lo
 // term, ~2^-16 relative, is dropped).  Plain mode keeps hi*hi only.
 //
-// Both operands are converted once, before the contraction, into records of
-// 16 beams (see kernels.hpp): S per (pixel tile, K step), C per (probe, K
-// step).  A workgroup (one 16 x 16 pixel tile x 64 probes) then copies each K
-// step's records straight into LDS and feeds the MFMAs; the next K step's
-// global loads are in flight while the current step's MFMAs run.  With W
-// wavefronts (4 or 8), wave w owns tile rows (16/W)w .. (16/W)(w+1)-1 (16-pixel
-// MFMA column blocks) and all W 16-probe row blocks: 16 W probes per workgroup.
+// Operands are staged per K step (16 beams) as records: NP parts (hi, lo) x
+// (re, im) x two halves of 8 beams as bf16, one record per pixel or probe.
+// Both operands are converted once per call, before the contraction, into
+// records in global memory: C per (probe, K step), S per (K step, pixel) in
+// pixel-major order, so that a work tile at any phase reads each of its 16
+// rows of records as one contiguous 2 KB run.  A workgroup copies a K step's
+// records into LDS (S chunks permuted by tile pixel, see rec_key) and feeds
+// the MFMAs while the next step's loads are in flight.  (The alternative
+// PRISM_CONTRACT_PRESPLIT = 0 reads S in its FP32 layout and splits it on the
+// fly: no converted copy, but every phase tile converting its pixels again.)
+// With W wavefronts (4 or 8), wave w owns tile rows (16/W)w .. (16/W)(w+1)-1
+// (16-pixel MFMA column blocks) and all W 16-probe row blocks: 16 W probes
+// per workgroup.
+#ifndef PRISM_CONTRACT_PRESPLIT
+#define PRISM_CONTRACT_PRESPLIT 1   // 1: S as pixel-major split records; 0: FP32 S split on the fly
+#endif
 #ifndef PRISM_CONTRACT_WAVES
 #define PRISM_CONTRACT_WAVES 4   // wavefronts per contraction workgroup (4: 64 probes, 8: 128 probes)
 #endif
@@ -198,6 +215,8 @@ constexpr int NT = 64 * WAVES;        // threads per workgroup
 constexpr int PB = 16 / WAVES;        // tile rows (16-pixel MFMA column blocks) per wave
 constexpr int QB = 16 / PB;           // 16-probe row blocks
 constexpr int PC = 16 * QB;           // probes per workgroup
+constexpr int SH = NT / 256;          // threads per tile pixel in the S staging
+constexpr int HPT = 2 / SH;           // 8-beam halves of a K step converted per thread
 }
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -246,16 +265,33 @@ __device__ __forceinline__ void make_chunks(const float2 (&v)[8], int half, u32x
     }
 }
 
-// Split S: workgroup = (tile, K step), thread = pixel of the tile.
+// The record chunks of one 8-beam half of a pixel's K step, written to the
+// pixel's LDS record (chunk c at position c ^ key).
+template <int NP, int HALF>
+__device__ __forceinline__ void stage_s_half(const float2 (&v)[8], u32x4* rec, int key) {
+    u32x4 ch[NP * 4];
+    make_chunks<NP>(v, HALF, ch);
+#pragma unroll
+    for (int part = 0; part < NP; ++part)
+#pragma unroll
+        for (int reim = 0; reim < 2; ++reim) {
+            const int c = part * 4 + reim * 2 + HALF;
+            rec[c ^ key] = ch[c];
+        }
+}
+
+// Split S, pixel-major: out[(k plane + pixel) NCH + c] holds chunk c of the
+// record of K step k at pixel = y ns + x (chunks in order).  Thread = (K step,
+// pixel); consecutive threads read consecutive pixels of each beam plane and
+// write consecutive records.
 template <int NP>
 __global__ __launch_bounds__(WG) void k_split_s(const float2* __restrict__ S, u32x4* __restrict__ out, int n_beams,
-                                                int ns, int K) {
+                                                int plane, int K) {
     constexpr int NCH = NP * 4;
-    const int blk = blockIdx.x, tile = blk / K, k = blk % K;
-    const int ntx = ns / TILE, p = threadIdx.x;
-    const int y = (tile / ntx) * TILE + p / TILE, x = (tile % ntx) * TILE + p % TILE;
-    const size_t plane = (size_t)ns * ns;
-    const float2* src = S + (size_t)y * ns + x;
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= (int64_t)K * plane) return;
+    const int k = (int)(i / plane), pix = (int)(i % plane);
+    const float2* src = S + pix;
     float2 v[2][8];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -267,10 +303,21 @@ __global__ __launch_bounds__(WG) void k_split_s(const float2* __restrict__ S, u3
     u32x4 ch[NCH];
     make_chunks<NP>(v[0], 0, ch);
     make_chunks<NP>(v[1], 1, ch);
-    u32x4* rec = out + ((size_t)blk * 256 + p) * NCH;
-    const int key = rec_key<NP>(p);
+    u32x4* rec = out + i * NCH;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) rec[c ^ key] = ch[c];
+    for (int c = 0; c < NCH; ++c) rec[c] = ch[c];
+}
+
+hipError_t launch_split_s(int precision, const float2* S, void* Ssplit, int n_beams, int ns, hipStream_t st) {
+    const int K = ksteps_of(n_beams), plane = ns * ns;
+    const int64_t blocks = ((int64_t)K * plane + WG - 1) / WG;
+    if (precision == 1)
+        hipLaunchKernelGGL(k_split_s<2>, dim3((unsigned)blocks), dim3(WG), 0, st, S, static_cast<u32x4*>(Ssplit), n_beams,
+                           plane, K);
+    else
+        hipLaunchKernelGGL(k_split_s<1>, dim3((unsigned)blocks), dim3(WG), 0, st, S, static_cast<u32x4*>(Ssplit), n_beams,
+                           plane, K);
+    return hipGetLastError();
 }
 
 // Split C: thread = (probe, K step, half of 8 beams); records unpermuted.
@@ -301,16 +348,6 @@ __global__ __launch_bounds__(WG) void k_coefficients_split(u32x4* __restrict__ C
     }
 }
 
-hipError_t launch_split_s(int precision, const float2* S, void* Ssplit, int n_beams, int ns, hipStream_t st) {
-    const int K = ksteps_of(n_beams), ntx = ns / TILE;
-    dim3 grid((unsigned)(ntx * ntx * K));
-    if (precision == 1)
-        hipLaunchKernelGGL(k_split_s<2>, grid, dim3(WG), 0, st, S, static_cast<u32x4*>(Ssplit), n_beams, ns, K);
-    else
-        hipLaunchKernelGGL(k_split_s<1>, grid, dim3(WG), 0, st, S, static_cast<u32x4*>(Ssplit), n_beams, ns, K);
-    return hipGetLastError();
-}
-
 hipError_t launch_coefficients_split(int precision, void* Csplit, const double2* xy, const int2* beams,
                                      const float2* aberr, int n_probes, int n_beams, double inv_L, float amp,
                                      hipStream_t st) {
@@ -334,8 +371,7 @@ __global__ __launch_bounds__(mfmac::NT) __attribute__((amdgpu_waves_per_eu(2))) 
     using namespace mfmac;
     constexpr int NCH = NP * 4;                 // 16-byte chunks per record
     constexpr int CPT = PC * NCH / NT;          // C chunks staged per thread
-    constexpr int SPT = 256 * NCH / NT;         // S chunks staged per thread
-    __shared__ u32x4 Ss[256 * NCH];             // one K step of the tile (records as stored)
+    __shared__ u32x4 Ss[256 * NCH];             // one K step of the tile (pixel records, chunks permuted)
     __shared__ u32x4 Cl[PC * NCH];              // one K step of the probe chunk (records permuted)
     __shared__ int pidx[PC];
 
@@ -345,13 +381,12 @@ __global__ __launch_bounds__(mfmac::NT) __attribute__((amdgpu_waves_per_eu(2))) 
     float2* __restrict__ win = job.win;
     const int* __restrict__ tile_probes = job.tile_probes;
     const int2* __restrict__ corner = job.corner;
-    const int ns = job.ns, m = job.m, K = job.ksteps;
+    const int ns = job.ns, m = job.m, K = job.ksteps, n_beams = job.n_beams;
     const int t0 = job.tile_start[tile], t1 = job.tile_start[tile + 1];
     const int pc0 = t0 + chunk * PC;
     if (pc0 >= t1) return;
     const int np = min(PC, t1 - pc0);
-    const int ntx = ns / TILE;
-    const int tx0 = (tile % ntx) * TILE, ty0 = (tile / ntx) * TILE;
+    const int2 org = job.tile_origin[tile];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid < PC) pidx[tid] = tid < np ? tile_probes[pc0 + tid] : -1;
 
@@ -363,7 +398,35 @@ __global__ __launch_bounds__(mfmac::NT) __attribute__((amdgpu_waves_per_eu(2))) 
             accr[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
             acci[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-    const u32x4* __restrict__ Sg = static_cast<const u32x4*>(job.S) + (size_t)tile * K * 256 * NCH + tid;
+    const size_t plane = (size_t)ns * ns;
+#if PRISM_CONTRACT_PRESPLIT
+    // S staging: chunks q = tid + j NT of the step's 256 x NCH chunks, i.e.
+    // chunk sc of tile pixels sp0 + j PPJ, read by raw buffer loads from a
+    // scalar resource at the K step's records (byte offsets per chunk kept in
+    // registers; rows wrap periodically)
+    constexpr int SPT = 256 * NCH / NT, PPJ = NT / NCH;
+    const int sc = tid % NCH, sp0 = tid / NCH;
+    const int sx = (org.x + sp0 % TILE) & (ns - 1);
+    const int skey = rec_key<NP>(sp0);          // the same for every j: PPJ is a multiple of 8
+    int voff[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int sy = (org.y + (sp0 + j * PPJ) / TILE) & (ns - 1);
+        voff[j] = ((sy * ns + sx) * NCH + sc) * (int)sizeof(u32x4);
+    }
+#else
+    // S staging: tile pixel sp, 8-beam halves sh0 .. sh0 + HPT - 1 of each K
+    // step, read by raw buffer loads: a scalar resource at the K step's first
+    // beam plane, the pixel's byte offset in a plane (one register) and the
+    // beam's plane offset as a scalar, so the 16 loads of a step cost no
+    // address registers
+    // (sh0 is uniform over a wavefront: 0 with 4 wavefronts)
+    const int sp = tid & 255, sh0 = SH == 1 ? 0 : __builtin_amdgcn_readfirstlane((tid >> 8) * HPT);
+    const int sy = (org.y + sp / TILE) & (ns - 1), sx = (org.x + sp % TILE) & (ns - 1);
+    const int pix_off = (sy * ns + sx) * (int)sizeof(float2);
+    const int plane_bytes = (int)(plane * sizeof(float2));
+    const int skey = rec_key<NP>(sp);
+#endif
     __syncthreads();
     // C staging: chunk q = tid * CPT + j of the step's PC x NCH chunks
     const int crow = (tid * CPT) / NCH, cc0 = (tid * CPT) % NCH;
@@ -372,23 +435,64 @@ __global__ __launch_bounds__(mfmac::NT) __attribute__((amdgpu_waves_per_eu(2))) 
     const int ckey = rec_key<NP>(crow);
     const u32x4 zero = u32x4{0u, 0u, 0u, 0u};
 
-    u32x4 sreg[SPT], creg[CPT];
+    u32x4 creg[CPT];
+#if PRISM_CONTRACT_PRESPLIT
+    u32x4 sreg[SPT];
+    auto load_s = [&](int k) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<u32x4*>(static_cast<const u32x4*>(job.S) + (size_t)k * plane * NCH), (short)0, 0x7fffffff,
+            0x00020000);
 #pragma unroll
-    for (int j = 0; j < SPT; ++j) sreg[j] = Sg[j * NT];
+        for (int j = 0; j < SPT; ++j)
+            sreg[j] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff[j], 0, 0));
+    };
+    auto stage_s = [&]() {
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) Ss[(sp0 + j * PPJ) * NCH + (sc ^ skey)] = sreg[j];
+    };
+#else
+    float2 sv[HPT][8];
+    auto load_s = [&](int k) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float2*>(static_cast<const float2*>(job.S) + (size_t)k * KSTEP * plane), (short)0, 0x7fffffff,
+            0x00020000);
+        const bool full = k * KSTEP + KSTEP <= n_beams;   // every beam of the step exists (uniform)
+#pragma unroll
+        for (int h = 0; h < HPT; ++h)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int jb = (SH == 1 ? h : sh0) * 8 + j;
+                sv[h][j] = full || k * KSTEP + jb < n_beams
+                               ? __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, pix_off, jb * plane_bytes, 0))
+                               : make_float2(0.f, 0.f);
+            }
+    };
+    // record chunks of the staged halves (the half index must be a
+    // compile-time constant: it selects registers)
+    auto stage_s = [&]() {
+        if constexpr (SH == 1) {
+            stage_s_half<NP, 0>(sv[0], Ss + sp * NCH, skey);
+            stage_s_half<NP, 1>(sv[HPT - 1], Ss + sp * NCH, skey);
+        } else if (sh0 == 0) {
+            stage_s_half<NP, 0>(sv[0], Ss + sp * NCH, skey);
+        } else {
+            stage_s_half<NP, 1>(sv[0], Ss + sp * NCH, skey);
+        }
+    };
+#endif
+    load_s(0);
 #pragma unroll
     for (int j = 0; j < CPT; ++j) creg[j] = cq >= 0 ? Cg[j] : zero;
 
     const int col = lane & 15, g = lane >> 4;   // MFMA operand lane roles
     const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
     for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int j = 0; j < SPT; ++j) Ss[tid + j * NT] = sreg[j];
+        stage_s();
 #pragma unroll
         for (int j = 0; j < CPT; ++j) Cl[crow * NCH + ((cc0 + j) ^ ckey)] = creg[j];
         __syncthreads();
         if (k + 1 < K) {
-#pragma unroll
-            for (int j = 0; j < SPT; ++j) sreg[j] = Sg[(size_t)(k + 1) * 256 * NCH + j * NT];
+            load_s(k + 1);
 #pragma unroll
             for (int j = 0; j < CPT; ++j) creg[j] = cq >= 0 ? Cg[(size_t)(k + 1) * NCH + j] : zero;
         }
@@ -443,7 +547,7 @@ __global__ __launch_bounds__(mfmac::NT) __attribute__((amdgpu_waves_per_eu(2))) 
             const int2 c0 = corner[q];
 #pragma unroll
             for (int pb = 0; pb < PB; ++pb) {
-                const int py = ty0 + PB * wave + pb, px = tx0 + col;
+                const int py = (org.y + PB * wave + pb) & (ns - 1), px = (org.x + col) & (ns - 1);
                 const int v = (py - c0.y) & (ns - 1);
                 const int u = (px - c0.x) & (ns - 1);
                 if (v < m && u < m) {
@@ -455,6 +559,9 @@ __global__ __launch_bounds__(mfmac::NT) __attribute__((amdgpu_waves_per_eu(2))) 
             }
         }
 }
+
+int contract_probe_chunk() { return mfmac::PC; }
+bool contract_reads_split_s() { return PRISM_CONTRACT_PRESPLIT != 0; }
 
 hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_jobs, hipStream_t st) {
     const int pc = precision == 0 ? fp32c::PC : mfmac::PC;
@@ -470,6 +577,7 @@ hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_
             job.win = a.win;
             job.tile_start = a.tile_start;
             job.tile_probes = a.tile_probes;
+            job.tile_origin = a.tile_origin;
             job.corner = a.corner;
             job.n_beams = a.n_beams;
             job.ns = a.ns;
@@ -484,6 +592,7 @@ hipError_t launch_contract_batch(int precision, const ContractArgs* jobs, int n_
         }
         b.n_blocks = blocks;
         b.per_xcd = (blocks + 7) / 8;
+        if (blocks == 0) continue;
         dim3 grid((unsigned)(8 * b.per_xcd));
         if (precision == 0)
             hipLaunchKernelGGL(k_contract_fp32, grid, dim3(WG), 0, st, b);
@@ -524,16 +633,28 @@ struct WindowBatch {
     WindowJob job[MAX_JOBS];
 };
 
-// The window sits unpadded in LDS with row stride M + 16/LPT, so that the
-// strided column reads of the 16 lanes of a 64-bit access (16/LPT columns of
-// LPT lanes each) fall in distinct banks; the transforms exchange through a
-// private padded buffer per transform instead of the window itself.
+// The window sits in LDS with an odd row stride RS of at least the padded
+// exchange length and with that many rows (more than M), so that each row
+// transform and each column transform exchanges in place, through the
+// padded slots of its own row or column: no separate exchange buffers, so
+// the 128-point windows take 16 wavefronts per workgroup in the LDS that
+// would otherwise hold 4 wavefronts' exchange buffers.  The odd stride keeps
+// the strided column accesses of 16 lanes in distinct banks.
 template <int M>
-__global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
+struct WinCfg {
     using F = Fft<M>;
-    constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, ROW = M + 16 / LPT;
-    __shared__ float2 buf[M * ROW];
-    __shared__ float2 xch[4 * G * F::LDS];
+    static constexpr int NW = M >= 128 ? 16 : 4;              // wavefronts per workgroup
+    static constexpr int NT = 64 * NW;
+    static constexpr int RS = F::LDS | 1;                     // row stride (float2), odd
+    static constexpr int ROWS = F::LDS;                       // rows (the column exchanges use all)
+};
+
+template <int M>
+__global__ __launch_bounds__(WinCfg<M>::NT) void k_window_detect(WindowBatch batch) {
+    using C = WinCfg<M>;
+    using F = typename C::F;
+    constexpr int E = F::E, LPT = F::LPT, G = 64 / LPT, NW = C::NW, NT = C::NT, RS = C::RS;
+    __shared__ float2 buf[C::ROWS * RS];
     int jj = 0;
 #pragma unroll
     for (int k = 1; k < MAX_JOBS; ++k)
@@ -552,64 +673,65 @@ __global__ __launch_bounds__(WG) void k_window_detect(WindowBatch batch) {
     const float2* w = win + (size_t)p * M * M;
     {
         // batches of loads in flight before their LDS stores
-        constexpr int NLD = (M * M + WG - 1) / WG, BATCH = NLD < 16 ? NLD : 16;
+        constexpr int NLD = (M * M + NT - 1) / NT, BATCH = NLD < 16 ? NLD : 16;
         static_assert(NLD % BATCH == 0, "load batches must divide the window");
 #pragma unroll 1
         for (int k0 = 0; k0 < NLD; k0 += BATCH) {
             float2 ld[BATCH];
 #pragma unroll
             for (int k = 0; k < BATCH; ++k) {
-                const int idx = tid + (k0 + k) * WG;
+                const int idx = tid + (k0 + k) * NT;
                 if (idx < M * M) ld[k] = w[idx];
             }
 #pragma unroll
             for (int k = 0; k < BATCH; ++k) {
-                const int idx = tid + (k0 + k) * WG;
-                if (idx < M * M) buf[(idx / M) * ROW + idx % M] = ld[k];
+                const int idx = tid + (k0 + k) * NT;
+                if (idx < M * M) buf[(idx / M) * RS + idx % M] = ld[k];
             }
         }
     }
     __syncthreads();
     typename F::Twiddles tw;
     tw.load(tw_m, lt);
-    float2* const x = xch + (wave * G + g) * F::LDS;
-    // rows
-    for (int r0 = wave * G; r0 < M; r0 += 4 * G) {
-        float2* row = buf + (r0 + g) * ROW;
+    // rows, each exchanged in its own padded row
+    for (int r0 = wave * G; r0 < M; r0 += NW * G) {
+        float2* row = buf + (r0 + g) * RS;
         float2 v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = row[lt + LPT * i];
-        F::template run<-1>(v, x, tw, lt);
+        F::template run_x<-1>(v, typename F::RowX{row}, tw, lt);
+        F::sync();
 #pragma unroll
         for (int i = 0; i < E; ++i) row[lt + LPT * i] = v[i];
     }
     __syncthreads();
-    // columns, then intensity in place
+    // columns, each exchanged in its own padded column, then intensity in place
     const float scale = 1.0f / ((float)M * (float)M * (float)M * (float)M);
-    for (int c0 = wave * G; c0 < M; c0 += 4 * G) {
+    for (int c0 = wave * G; c0 < M; c0 += NW * G) {
         float2* col = buf + c0 + g;
         float2 v[E];
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = col[(lt + LPT * i) * ROW];
-        F::template run<-1>(v, x, tw, lt);
+        for (int i = 0; i < E; ++i) v[i] = col[(lt + LPT * i) * RS];
+        F::template run_x<-1>(v, typename F::template StrideX<RS>{col}, tw, lt);
+        F::sync();
 #pragma unroll
-        for (int i = 0; i < E; ++i) col[(lt + LPT * i) * ROW] = make_float2(cnorm(v[i]) * scale, 0.f);
+        for (int i = 0; i < E; ++i) col[(lt + LPT * i) * RS] = make_float2(cnorm(v[i]) * scale, 0.f);
     }
     __syncthreads();
     if (diff) {
         // the 4D output takes the same scale and accumulation as the 3D one
         float* d = diff + (size_t)p * M * M;
-        for (int idx = tid; idx < M * M; idx += WG) {
-            const float v = job.scale * buf[(idx / M) * ROW + idx % M].x;
+        for (int idx = tid; idx < M * M; idx += NT) {
+            const float v = job.scale * buf[(idx / M) * RS + idx % M].x;
             d[idx] = job.accumulate ? d[idx] + v : v;
         }
     }
     if (!out) return;
-    for (int b = wave; b < n_bins; b += 4) {
+    for (int b = wave; b < n_bins; b += NW) {
         float s = 0.f;
         for (int k = bin_start[b] + lane; k < bin_start[b + 1]; k += 64) {
             int pix = perm[k];
-            s += buf[(pix / M) * ROW + pix % M].x;
+            s += buf[(pix / M) * RS + pix % M].x;
         }
         s = wave_sum(s);
         if (lane == 0) {
@@ -632,7 +754,7 @@ static hipError_t window_m(const WindowArgs* jobs, int n_jobs, hipStream_t st) {
             blocks += a.n_probes;
         }
         if (blocks == 0) continue;
-        hipLaunchKernelGGL((k_window_detect<M>), dim3((unsigned)blocks), dim3(WG), 0, st, b);
+        hipLaunchKernelGGL((k_window_detect<M>), dim3((unsigned)blocks), dim3(WinCfg<M>::NT), 0, st, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -9,7 +9,11 @@ scan each) arrive over time.  The loop
   request that fits may pass a waiting one, until the waiting one has been
   passed `aging` times;
 * builds each admitted request's potential and S-matrix on that request's own
-  HIP stream, so builds of different requests overlap on the device;
+  HIP stream, so builds of different requests overlap on the device; a
+  build is issued one beam range at a time (about 2^30 beam-pixels each,
+  `prism_build_smatrix_range`), the next range only once the previous one
+  has finished, so other requests' work never queues behind a whole large
+  build on a shared hardware queue;
 * keeps every built S-matrix resident until its probes are done, and
   synthesises probes of all built requests together: each scheduling step
   issues one batched synthesis (prism_probe_outputs_batched) over up to
@@ -187,7 +191,7 @@ class GpuExecutor:
     """Runs requests with libprism on the current HIP device."""
 
     def __init__(self, precision: int, probe_chunk_bytes: int = 1 << 30, build_ws_bytes: int = 16 << 30,
-                 split_limit_bytes: int = 8 << 30, jobs_per_request: int = 4):
+                 split_limit_bytes: int = 8 << 30, jobs_per_request: int = 4, range_pixels: int = 1 << 30):
         import torch
 
         from . import api
@@ -201,6 +205,8 @@ class GpuExecutor:
         # chunks (prism_probe_outputs_chunked) instead of in the shared batch
         self.split_limit_bytes = split_limit_bytes
         self.jobs_per_request = jobs_per_request      # must match the scheduler's
+        # beams of one build range: about range_pixels beam-pixels (n^2 each)
+        self.range_pixels = range_pixels
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
 
@@ -247,25 +253,51 @@ class GpuExecutor:
     def start(self, req: Request):
         torch, api = self.torch, self.api
         info = req.info
+        d = info["desc"]
         st = torch.cuda.Stream()
         info["stream"] = st
         pos, sp, species = req.sample() if callable(req.sample) else req.sample
         with torch.cuda.stream(st):
-            info["plans"] = [api.prism_probe_plan_upload(info["desc"], c, req.dalpha) for c in info["chunks"]]
-            V = api.prism_project_potential(pos, sp, species, info["grid"])
-            ws = torch.empty(info["desc"].build_ws_bytes, dtype=torch.uint8, device="cuda")
-            S = api.prism_build_smatrix(info["desc"], V, ws=ws)
+            info["plans"] = [api.prism_probe_plan_upload(d, c, req.dalpha) for c in info["chunks"]]
+            info["V"] = api.prism_project_potential(pos, sp, species, info["grid"])
+            info["build_ws"] = torch.empty(d.build_ws_bytes, dtype=torch.uint8, device="cuda")
+            info["S"] = torch.empty((d.n_beams, d.ns, d.ns), dtype=torch.complex64, device="cuda")
             info["out"] = torch.empty((req.n_probes, info["n_bins"]), dtype=torch.float32, device="cuda")
+        info["range_beams"] = max(16, min(d.beam_batch or d.n_beams, self.range_pixels // (req.n * req.n)))
+        info["next_beam"] = 0
+        info["built_event"] = None
+        self._next_range(req)
+
+    def _next_range(self, req: Request):
+        """Issue the request's next beam range on its stream."""
+        torch, api = self.torch, self.api
+        info = req.info
+        d, st = info["desc"], info["stream"]
+        b0 = info["next_beam"]
+        cnt = min(info["range_beams"], d.n_beams - b0)
+        with torch.cuda.stream(st):
+            api.prism_build_smatrix_range(d, info["V"], info["S"], b0, cnt, ws=info["build_ws"])
             ev = torch.cuda.Event()
             ev.record(st)
-        ws.record_stream(st)
-        V.record_stream(st)
-        del ws, V
-        info["S"] = S
+        info["next_beam"] = b0 + cnt
         info["built_event"] = ev
+        if info["next_beam"] == d.n_beams:
+            # the last range is queued: the potential and the workspace are
+            # released once the stream has used them
+            for k in ("V", "build_ws"):
+                info[k].record_stream(st)
+                del info[k]
 
     def is_built(self, req: Request) -> bool:
-        return req.info["built_event"].query()
+        """True once every range has finished; issues the next range when the
+        previous one has."""
+        info = req.info
+        if not info["built_event"].query():
+            return False
+        if info["next_beam"] < info["desc"].n_beams:
+            self._next_range(req)
+            return False
+        return True
 
     # -- synthesis --
     def synthesize(self, batch):
@@ -370,7 +402,12 @@ def summarize(sched: Scheduler, wall: float):
     done = sched.done
     lat = np.array([r.latency for r in done]) if done else np.zeros(1)
     probes = sum(r.n_probes for r in done)
+    by_grid = {}
+    for n in sorted({r.n for r in done}):
+        ln = np.array([r.latency for r in done if r.n == n])
+        by_grid[str(n)] = {"requests": int(len(ln)), "p50_latency_s": float(np.percentile(ln, 50)),
+                           "p99_latency_s": float(np.percentile(ln, 99))}
     return {"requests": len(done), "rejected": len(sched.rejected), "probes": probes,
             "wall_s": wall, "probes_per_s": probes / wall if wall > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
-            "peak_hbm_reserved": sched.peak_used}
+            "latency_by_grid": by_grid, "peak_hbm_reserved": sched.peak_used}

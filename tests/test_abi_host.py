@@ -123,6 +123,32 @@ def test_detector_default_bins_query_matches_oracle(cfg, dalpha):
         assert e.value.code == P.PRISM_E_INVAL
 
 
+def test_probe_plan_work_tiles_follow_the_scan_lattice():
+    """On the benchmark scans (probes every 4 S-grid pixels, 128-pixel
+    windows) every window is tiled at its own phase: exactly (128/16)^2 = 64
+    work tiles per probe, and every work tile holds 64 probes, one full
+    workgroup of the MFMA contraction (no products outside a window, no
+    partly filled probe chunk)."""
+    P = _lib()
+    for name in ("prism_f4_np_1024", "prism_f8_np_2048"):
+        w = W.WORKLOADS[name]
+        g = P.prism_grid_init(w.cell, w.dz, w.n)
+        d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+        xy = W.scan_positions(w.cell, *w.scan)
+        p = P.prism_probe_plan_init(d, xy)
+        assert d.m_win == 128
+        assert p.n_entries == 64 * len(xy), name
+        assert p.max_per_tile == 64 and p.n_tiles == len(xy), name
+    # irregular positions: one tiling phase per corner offset would leave the
+    # 64-probe chunks nearly empty, so the plan keeps the 16-aligned grid,
+    # where a window not aligned to it overlaps 9 tiles per axis
+    rng = np.random.default_rng(5)
+    xr = rng.uniform(0.0, w.cell[0], size=(4096, 2))
+    p = P.prism_probe_plan_init(d, xr)
+    assert 64 * len(xr) < p.n_entries <= 81 * len(xr)
+    assert p.n_tiles <= (d.ns // 16) ** 2
+
+
 def test_probe_plan_sizes():
     P = _lib()
     w = W.WORKLOADS["prism_f2_sc_256"]

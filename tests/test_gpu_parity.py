@@ -402,6 +402,41 @@ def test_multi_stream_build_equals_one_stream(P, streams, beam_batch):
     assert np.linalg.norm(a[-1] - ref) / np.linalg.norm(ref) <= TOL
 
 
+# ------------------------------------------------------ build in beam ranges --
+@pytest.mark.parametrize("streams,beam_batch,ranges", [(1, 0, (5, 30)), (2, 0, (1, 17, 40)), (2, 9, (13, 13)),
+                                                       (3, 7, (50,))])
+def test_build_in_beam_ranges_equals_whole_build(P, streams, beam_batch, ranges):
+    """prism_build_smatrix_range over consecutive ranges (ragged against the
+    beam batch) writes exactly the layers of the whole build, bit for bit,
+    and leaves the layers outside its range untouched."""
+    import torch
+    w, pos, sp = W.small_workload(n=128, cell=(20.0, 20.0, 8.0), n_atoms=40, f=2, seed=31)
+    g, V = _gpu_potential(P, w, pos, sp)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, 2, beam_batch=beam_batch)
+    say(f"S-matrix by beam ranges {ranges} (n_beams={d.n_beams}, beam_batch={beam_batch}, streams={streams})")
+    try:
+        P.prism_set_build_streams(streams)
+        whole = P.prism_build_smatrix(d, V)
+        S = torch.full((d.n_beams, d.ns, d.ns), complex(7.0, -3.0), dtype=torch.complex64, device="cuda")
+        b0 = 0
+        for r in list(ranges):
+            cnt = min(r, d.n_beams - b0)
+            P.prism_build_smatrix_range(d, V, S, b0, cnt)
+            b0 += cnt
+        torch.cuda.synchronize()
+    finally:
+        P.prism_set_build_streams(2)
+    a, b = whole.cpu().numpy(), S.cpu().numpy()
+    assert np.array_equal(a[:b0], b[:b0])
+    assert np.all(b[b0:] == np.complex64(complex(7.0, -3.0)))
+    ct = P._lib.ctypes
+    ws = torch.empty(d.build_ws_bytes, dtype=torch.uint8, device="cuda")
+    for first, cnt in ((-1, 2), (0, d.n_beams + 1), (d.n_beams - 1, 2)):
+        rc = P.lib.prism_build_smatrix_range(ct.byref(d), ct.c_void_p(V.data_ptr()), ct.c_void_p(S.data_ptr()),
+                                             first, cnt, ct.c_void_p(ws.data_ptr()), ws.numel(), None)
+        assert rc == P.PRISM_E_INVAL
+
+
 # -------------------------------------------------------- diagnostic copy --
 def test_device_copy(P):
     import torch

@@ -33,7 +33,7 @@ def _run(reqs, prec, **kw):
     import torch
     from paper_1706_08563_amd.serve import GpuExecutor, Scheduler, serve
     ex = GpuExecutor(prec, probe_chunk_bytes=kw.pop("chunk", 1 << 30),
-                     split_limit_bytes=kw.pop("split_limit", 8 << 30))
+                     split_limit_bytes=kw.pop("split_limit", 8 << 30), range_pixels=kw.pop("range_pixels", 1 << 30))
     sched = Scheduler(int(64e9), **kw)
     serve(reqs, ex, sched)
     torch.cuda.synchronize()
@@ -85,3 +85,18 @@ def test_beam_chunked_requests_in_the_mix():
         err = O.rel_err(a.result, b.result)
         say(f"  request {a.rid} (n={a.n}, beam chunk {a.info.get('beam_chunk')}): rel diff {err:.3e}")
         assert err <= 1e-5
+
+
+def test_builds_in_beam_ranges_equal_whole_builds():
+    """With builds issued a few beams at a time (every request's S-matrix in
+    several ranges, interleaved with the other requests' ranges and
+    syntheses) every result equals the one-range build bit for bit."""
+    say("serving: builds in small beam ranges vs one range per request")
+    a = _requests()
+    _run(a, 1, max_building=4, max_jobs=8, range_pixels=16 * 128 * 128)
+    assert max(r.info["range_beams"] for r in a) < max(r.info["n_beams"] for r in a)
+    b = _requests()
+    _run(b, 1, max_building=4, max_jobs=8)
+    for x, y in zip(a, b):
+        say(f"  request {x.rid} (n={x.n}, {x.info['n_beams']} beams, ranges of {x.info['range_beams']})")
+        assert np.array_equal(x.result, y.result)
