@@ -661,6 +661,11 @@ def main():
     kernels["pass_a"]["GB_per_s"] = a_bytes / (kernels["pass_a"]["avg_ms"] * 1e-3) / 1e9
     kernels["pass_b"]["GB_per_s"] = b_bytes / (kernels["pass_b"]["avg_ms"] * 1e-3) / 1e9
     kernels["contract"]["TFLOP_per_s"] = c_flops / (kernels["contract"]["avg_ms"] * 1e-3) / 1e12
+    if prec != P.PRISM_FP32:
+        # MFMA work: three BF16 products per complex product in split mode, one in plain BF16
+        mw = kernels["contract"]["TFLOP_per_s"] * (3 if prec == P.PRISM_SPLIT_BF16X3 else 1)
+        kernels["contract"]["mfma_work_TFLOP_per_s"] = mw
+        kernels["contract"]["mfma_frac_of_bf16_peak"] = mw / PEAK_BF16_TFLOPS
     kernels["pass_a"]["TFLOP_per_s"] = pass_flops(n, B, n) / (kernels["pass_a"]["avg_ms"] * 1e-3) / 1e12
     kernels["pass_b"]["TFLOP_per_s"] = pass_flops(n, B, n // 2) / (kernels["pass_b"]["avg_ms"] * 1e-3) / 1e12
     dom = max(["pass_a", "pass_b", "contract"], key=lambda k: kernels[k]["ms_total"])

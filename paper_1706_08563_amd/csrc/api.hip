@@ -19,6 +19,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -300,18 +301,31 @@ struct TileCover {
         first = rel / 16;
         count = std::min((rel + M - 1) / 16 - first + 1, nt);   // a window as wide as the grid covers each tile once
     }
-    int key(int phx, int phy, int tx, int ty) const { return ((phy * nq + phx) * nt + ty) * nt + tx; }
+    int key(int ph, int tx, int ty) const { return (ph * nt + ty) * nt + tx; }
 };
 
-// Probe count of every (phase, tile) key for quantum Q.
-static void cover_counts(const TileCover& tc, const std::vector<int2>& corner, std::vector<int>& count) {
+// One probe's tiles under a TileCover: phase index and, per axis, the first
+// tile and the tile count.
+struct Span {
+    int ph, fx, nx, fy, ny;
+};
+
+// Spans of every probe and the probe count of every (phase, tile) key.
+static void cover_counts(const TileCover& tc, const std::vector<int2>& corner, std::vector<Span>& spans,
+                         std::vector<int>& count) {
+    spans.resize(corner.size());
     count.assign((size_t)tc.nq * tc.nq * tc.nt * tc.nt, 0);
-    for (const int2& c : corner) {
-        int px, fx, nx, py, fy, ny;
-        tc.span(c.x, px, fx, nx);
-        tc.span(c.y, py, fy, ny);
-        for (int a = 0; a < ny; ++a)
-            for (int b = 0; b < nx; ++b) count[tc.key(px, py, (fx + b) % tc.nt, (fy + a) % tc.nt)]++;
+    const int wrap = tc.nt - 1;
+    for (size_t p = 0; p < corner.size(); ++p) {
+        Span& sp = spans[p];
+        int phx, phy;
+        tc.span(corner[p].x, phx, sp.fx, sp.nx);
+        tc.span(corner[p].y, phy, sp.fy, sp.ny);
+        sp.ph = phy * tc.nq + phx;
+        for (int a = 0; a < sp.ny; ++a) {
+            int* row = count.data() + (size_t)tc.key(sp.ph, 0, (sp.fy + a) & wrap);
+            for (int b = 0; b < sp.nx; ++b) row[(sp.fx + b) & wrap]++;
+        }
     }
 }
 
@@ -336,27 +350,43 @@ int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, 
         int cx = centre_of(x, L, n), cy = centre_of(y, L, n);
         h.corner[p] = make_int2((cx - M / 2) & (ns - 1), (cy - M / 2) & (ns - 1));
     }
-    // the quantum whose work tiles need the fewest workgroups of the MFMA
-    // contraction's probe chunk (ties: the coarser tiling)
+    // The quantum whose work tiles need the fewest workgroups of the MFMA
+    // contraction's probe chunk.  Exact phases (Q = 1) give every window the
+    // fewest tiles; when their probe chunks are also all full no tiling needs
+    // fewer workgroups, and the aligned grid (Q = 16) is not evaluated.
     const int pc = contract_probe_chunk();
-    TileCover tc{ns / 16, 1, 16, M, ns};
-    std::vector<int> count;
-    long long best = -1;
-    for (int Q : {16, 1}) {
-        TileCover t{ns / 16, 16 / Q, Q, M, ns};
-        cover_counts(t, h.corner, count);
+    auto cost_of = [&](const std::vector<int>& count, long long& entries) {
         long long cost = 0;
-        for (int c : count) cost += (c + pc - 1) / pc;
-        if (best < 0 || cost < best) {
-            best = cost;
-            tc = t;
+        entries = 0;
+        for (int c : count) {
+            cost += (c + pc - 1) / pc;
+            entries += c;
+        }
+        return cost;
+    };
+    TileCover tc{ns / 16, 16, 1, M, ns};
+    std::vector<Span> spans;
+    std::vector<int> count;
+    cover_counts(tc, h.corner, spans, count);
+    long long entries = 0;
+    const long long cost1 = cost_of(count, entries);
+    if (cost1 > (entries + pc - 1) / pc) {
+        TileCover t16{ns / 16, 1, 16, M, ns};
+        std::vector<Span> spans16;
+        std::vector<int> count16;
+        cover_counts(t16, h.corner, spans16, count16);
+        long long e16 = 0;
+        if (cost_of(count16, e16) <= cost1) {
+            tc = t16;
+            spans.swap(spans16);
+            count.swap(count16);
         }
     }
-    cover_counts(tc, h.corner, count);
     std::vector<std::pair<uint64_t, int>> order;   // (position, phase) sort key, key
+    const int nt2 = tc.nt * tc.nt;
     for (int k = 0; k < (int)count.size(); ++k) {
         if (!count[k]) continue;
-        const int tx = k % tc.nt, ty = (k / tc.nt) % tc.nt, ph = k / (tc.nt * tc.nt);
+        const int tx = k % tc.nt, ty = (k / tc.nt) % tc.nt, ph = k / nt2;
         order.emplace_back(((uint64_t)morton(ty, tx) << 16) | (uint64_t)ph, k);
     }
     std::sort(order.begin(), order.end());
@@ -367,22 +397,48 @@ int probe_host(const prism_smatrix_desc* d, const double* xy, int64_t n_probes, 
     max_per_tile = 0;
     for (int t = 0; t < n_tiles; ++t) {
         const int k = order[t].second;
-        const int tx = k % tc.nt, ty = (k / tc.nt) % tc.nt, ph = k / (tc.nt * tc.nt);
+        const int tx = k % tc.nt, ty = (k / tc.nt) % tc.nt, ph = k / nt2;
         const int phx = ph % tc.nq, phy = ph / tc.nq;
         slot[k] = t;
         h.tile_start[t + 1] = h.tile_start[t] + count[k];
         h.tile_origin[t] = make_int2((phx * tc.Q + 16 * tx) & (ns - 1), (phy * tc.Q + 16 * ty) & (ns - 1));
         max_per_tile = std::max(max_per_tile, count[k]);
     }
+    // probe lists, filled phase by phase (probes of one phase in their order)
+    // so that consecutive probes land on neighbouring work tiles
+    const int nph = tc.nq * tc.nq, wrap = tc.nt - 1;
+    std::vector<int> by_phase(n_probes), ph_start(nph + 1, 0);
+    for (const Span& sp : spans) ph_start[sp.ph + 1]++;
+    for (int q = 0; q < nph; ++q) ph_start[q + 1] += ph_start[q];
+    {
+        std::vector<int> pos(ph_start.begin(), ph_start.end() - 1);
+        for (int64_t p = 0; p < n_probes; ++p) by_phase[pos[spans[p].ph]++] = (int)p;
+    }
     h.tile_probes.assign(h.tile_start[n_tiles], 0);
-    std::vector<int> fill(h.tile_start.begin(), h.tile_start.end() - 1);
-    for (int64_t p = 0; p < n_probes; ++p) {
-        int px, fx, nx, py, fy, ny;
-        tc.span(h.corner[p].x, px, fx, nx);
-        tc.span(h.corner[p].y, py, fy, ny);
-        for (int a = 0; a < ny; ++a)
-            for (int b = 0; b < nx; ++b)
-                h.tile_probes[fill[slot[tc.key(px, py, (fx + b) % tc.nt, (fy + a) % tc.nt)]]++] = (int)p;
+    // the phases' work tiles are disjoint, so phases fill in parallel, each
+    // with its own write positions (a phase's keys are one contiguous block)
+    auto fill_phases = [&](int q0, int q1) {
+        std::vector<int> fill(nt2);
+        for (int q = q0; q < q1; ++q) {
+            const int* sq = slot.data() + (size_t)q * nt2;
+            for (int k = 0; k < nt2; ++k) fill[k] = sq[k] >= 0 ? h.tile_start[sq[k]] : 0;
+            for (int i = ph_start[q]; i < ph_start[q + 1]; ++i) {
+                const int p = by_phase[i];
+                const Span& sp = spans[p];
+                for (int a = 0; a < sp.ny; ++a) {
+                    int* frow = fill.data() + (size_t)((sp.fy + a) & wrap) * tc.nt;
+                    for (int b = 0; b < sp.nx; ++b) h.tile_probes[frow[(sp.fx + b) & wrap]++] = p;
+                }
+            }
+        }
+    };
+    const int nthr = std::min<int>(nph, std::max(1u, std::min(8u, std::thread::hardware_concurrency())));
+    if (nthr > 1 && n_probes >= 4096) {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthr; ++t) pool.emplace_back(fill_phases, nph * t / nthr, nph * (t + 1) / nthr);
+        for (std::thread& th : pool) th.join();
+    } else {
+        fill_phases(0, nph);
     }
     bin_tables(d->lambda, L / d->f, d->alpha_aa, dalpha, n_bins, M, dmap, h.perm, h.bin_start);
     h.tw_m = twiddle_table(M);
@@ -799,6 +855,51 @@ int prism_build_smatrix_range(const prism_smatrix_desc* d, const float* V, void*
 // -------------------------------------------------------- probe outputs --
 // Plan of either detector: annular bins of width dalpha (dmap NULL) or the
 // caller's map of the window grid (dalpha recorded as 0).
+// The host tables of the last plan made on this thread, with every input they
+// depend on, so that uploading that plan right after making it does not
+// compute them again (inputs compared exactly, positions included).
+struct PlanMemo {
+    bool valid = false;
+    int n, f, ns, m_win, n_bins;
+    double L, lambda, alpha_max, alpha_aa, dalpha, C1, C3;
+    std::vector<int32_t> dmap;
+    ProbeHost h;
+    int maxpt = 0;
+};
+thread_local PlanMemo t_plan_memo;
+
+static bool memo_matches(const PlanMemo& m, const prism_smatrix_desc* d, const double* xy, int64_t n_probes,
+                         double dalpha, int n_bins, double C1, double C3, const int32_t* dmap) {
+    if (!m.valid || m.n != d->grid.n || m.f != d->f || m.ns != d->ns || m.m_win != d->m_win || m.n_bins != n_bins ||
+        m.L != d->grid.cell[0] || m.lambda != d->lambda || m.alpha_max != d->alpha_max || m.alpha_aa != d->alpha_aa ||
+        m.dalpha != dalpha || m.C1 != C1 || m.C3 != C3 || (int64_t)m.h.xy.size() != n_probes ||
+        m.dmap.empty() != (dmap == nullptr))
+        return false;
+    if (dmap && std::memcmp(m.dmap.data(), dmap, m.dmap.size() * sizeof(int32_t)) != 0) return false;
+    return n_probes == 0 || std::memcmp(m.h.xy.data(), xy, (size_t)n_probes * sizeof(double2)) == 0;
+}
+
+static void memo_store(const prism_smatrix_desc* d, double dalpha, int n_bins, double C1, double C3,
+                       const int32_t* dmap, ProbeHost&& h, int maxpt) {
+    PlanMemo& m = t_plan_memo;
+    m.valid = true;
+    m.n = d->grid.n;
+    m.f = d->f;
+    m.ns = d->ns;
+    m.m_win = d->m_win;
+    m.n_bins = n_bins;
+    m.L = d->grid.cell[0];
+    m.lambda = d->lambda;
+    m.alpha_max = d->alpha_max;
+    m.alpha_aa = d->alpha_aa;
+    m.dalpha = dalpha;
+    m.C1 = C1;
+    m.C3 = C3;
+    m.dmap.assign(dmap, dmap ? dmap + (size_t)d->m_win * d->m_win : dmap);
+    m.h = std::move(h);
+    m.maxpt = maxpt;
+}
+
 static int probe_plan_make(const prism_smatrix_desc* d, const double* probe_xy, int64_t n_probes, double dalpha,
                            int32_t n_bins, const int32_t* dmap, const prism_aberrations* ab, prism_probe_plan* plan) {
     int rc = check_desc(d);
@@ -846,6 +947,7 @@ static int probe_plan_make(const prism_smatrix_desc* d, const double* probe_xy, 
     split_s_carve(d, w);
     p.ws_bytes = w.off + 256;
     *plan = p;
+    memo_store(d, dalpha, n_bins, C1, C3, dmap, std::move(h), maxpt);
     return PRISM_OK;
 }
 
@@ -874,10 +976,18 @@ static int probe_plan_put(const prism_smatrix_desc* d, const double* probe_xy, c
     } else if (!(plan->dalpha > 0)) {
         return fail(PRISM_E_INVAL, "probe plan upload: the plan was made for a detector map; upload it with that map");
     }
-    ProbeHost h;
-    int maxpt = 0;
-    rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, plan->C1, plan->C3, dmap, h, maxpt);
-    if (rc) return rc;
+    if (plan->n_probes > 0 && !probe_xy) return fail(PRISM_E_INVAL, "probe plan upload: NULL positions");
+    ProbeHost local;
+    const ProbeHost* hp = &t_plan_memo.h;
+    int maxpt = t_plan_memo.maxpt;
+    if (!memo_matches(t_plan_memo, d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, plan->C1, plan->C3,
+                      dmap)) {
+        rc = probe_host(d, probe_xy, plan->n_probes, plan->dalpha, plan->n_bins, plan->C1, plan->C3, dmap, local,
+                        maxpt);
+        if (rc) return rc;
+        hp = &local;
+    }
+    const ProbeHost& h = *hp;
     // every size the kernels and the workspace depend on must be the plan's
     if ((int64_t)h.tile_probes.size() != plan->n_entries || (int)h.perm.size() != plan->n_binned ||
         maxpt != plan->max_per_tile || (int64_t)h.tile_start.size() - 1 != plan->n_tiles)
