@@ -292,7 +292,8 @@ def serving_report(args, n_requests, grids, loads, seed=4, quiet=False):
             reqs.append(r)
         log(f"[{tag}] serving {len(reqs)} requests at {rate:.3f}/s, budget {cap / 1e9:.1f} GB")
         ex = SV.GpuExecutor(prec, jobs_per_request=4)
-        sched = SV.Scheduler(cap, max_building=4, max_jobs=24, jobs_per_request=4)
+        # batch cost: 2.5e12 complex multiply-adds, ~50 ms of split-BF16 contraction
+        sched = SV.Scheduler(cap, max_building=4, max_jobs=24, jobs_per_request=4, batch_cost=2.5e12)
         t0 = time.perf_counter()
         SV.serve(reqs, ex, sched, on_done=None if quiet else
                  lambda r: log(f"  [{tag}] done {r.rid} n={r.n} f={r.f} S={r.n_slices} P={r.n_probes} "

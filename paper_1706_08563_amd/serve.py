@@ -57,6 +57,8 @@ class Request:
     chunks_total: int = 0
     chunks_done: int = 0
     chunks_issued: int = 0
+    chunk_cost: float = 1.0        # synthesis work of one probe chunk (any unit, set by the executor)
+    passed: int = 0                # batches formed without this request while it had chunks left
     t_admit: float = math.nan
     t_built: float = math.nan
     t_done: float = math.nan
@@ -82,7 +84,7 @@ class Scheduler:
     """Admission, bookkeeping and batch formation; no device state."""
 
     def __init__(self, capacity: int, max_building: int = 4, max_jobs: int = 24, aging: int = 8,
-                 jobs_per_request: int = 4):
+                 jobs_per_request: int = 4, batch_cost: float | None = None):
         self.capacity = int(capacity)
         self.used = 0
         self.max_building = max_building
@@ -91,6 +93,9 @@ class Scheduler:
         # probe chunks of one request per batch (bounds a request's share of
         # the batch workspace, which its footprint accounts for)
         self.jobs_per_request = jobs_per_request
+        # a batch takes further chunks only while its summed chunk_cost stays
+        # within this (None: no limit)
+        self.batch_cost = batch_cost
         self.queue: list[Request] = []
         self.building: list[Request] = []
         self.built: list[Request] = []
@@ -157,17 +162,32 @@ class Scheduler:
         self.built.append(req)
 
     def next_batch(self, chunks_left) -> list:
-        """Up to max_jobs (request, chunk index) pairs from built requests,
-        oldest request first, at most jobs_per_request per request.
-        `chunks_left(req)` gives the chunks not yet issued."""
-        batch = []
-        for req in sorted(self.built, key=lambda r: r.arrival):
+        """Up to max_jobs (request, chunk index) pairs from built requests, at
+        most jobs_per_request per request.  Requests with the least remaining
+        synthesis work (chunk_cost x chunks left) come first, except that a
+        request passed over `aging` times goes before all others (oldest
+        first); with batch_cost set, a chunk joins a non-empty batch only
+        while the batch's cost stays within it, so the chunks of a large
+        request form batches of their own instead of holding small requests'
+        chunks back.  `chunks_left(req)` gives the chunks not yet issued."""
+        ready = [r for r in self.built if len(chunks_left(r)) > 0]
+
+        def key(r):
+            starved = r.passed >= self.aging
+            return (not starved, r.arrival if starved else r.chunk_cost * len(chunks_left(r)), r.arrival)
+
+        batch, cost = [], 0.0
+        for req in sorted(ready, key=key):
             for k, c in enumerate(chunks_left(req)):
-                if len(batch) >= self.max_jobs:
-                    return batch
-                if k >= self.jobs_per_request:
+                if len(batch) >= self.max_jobs or k >= self.jobs_per_request:
+                    break
+                if batch and self.batch_cost is not None and cost + req.chunk_cost > self.batch_cost:
                     break
                 batch.append((req, c))
+                cost += req.chunk_cost
+        taken = {id(r) for r, _ in batch}
+        for r in ready:
+            r.passed = 0 if id(r) in taken else r.passed + 1
         return batch
 
     def chunk_done(self, req: Request, now: float) -> bool:
@@ -247,6 +267,9 @@ class GpuExecutor:
         req.info.update(grid=g, desc=d, chunks=chunks, n_bins=n_bins, n_beams=d.n_beams, m_win=d.m_win,
                         beam_batch=d.beam_batch or d.n_beams, beam_chunk=beam_chunk)
         req.chunks_total = len(chunks)
+        # complex multiply-adds of one chunk's contraction (the synthesis's
+        # dominant work), the unit of the scheduler's batch_cost
+        req.chunk_cost = float(d.n_beams) * d.m_win * d.m_win * len(chunks[0])
         return int(foot)
 
     # -- build --

@@ -152,3 +152,37 @@ def test_batches_take_at_most_jobs_per_request_chunks_of_one_request():
     issued = sorted(x for b in ex.batches for x in b)
     assert issued == sorted([(0, c) for c in range(11)] + [(1, c) for c in range(2)])
     assert len(sched.done) == 2
+
+
+def test_small_requests_are_batched_before_a_large_one_and_it_is_not_starved():
+    """Least remaining work first: the chunks of small requests that arrive
+    while a large request's chunks wait go out first, each batch's cost stays
+    within batch_cost (a large chunk goes alone), and aging lets the large
+    request through while small ones keep arriving."""
+    big = _req(0, 0.0, foot=10, chunks=6)
+    big.info["cost"] = 100.0
+    small = [_req(i, 0.0005 * i, foot=10, chunks=1) for i in range(1, 40)]
+    reqs = [big] + small
+
+    class CostExecutor(FakeExecutor):
+        def plan(self, req):
+            req.chunk_cost = req.info.get("cost", 1.0)
+            return super().plan(req)
+
+    clk = Clock()
+    ex = CostExecutor(clk)
+    sched = Scheduler(1000, max_building=40, max_jobs=8, aging=4, batch_cost=100.0)
+    serve(reqs, ex, sched, clock=clk, sleep=clk.sleep)
+    assert len(sched.done) == 40
+    for b in ex.batches:
+        if any(rid == 0 for rid, _ in b):
+            assert len(b) == 1                      # a large chunk fills a batch by itself
+        else:
+            assert len(b) <= 8
+    # the first small requests finish before the large one
+    assert sum(1 for r in small if r.t_done < big.t_done) > 10
+    # and the large one is not left to the end: aging gives it batches while
+    # small requests are still being served
+    first_big = min(i for i, b in enumerate(ex.batches) if any(rid == 0 for rid, _ in b))
+    last_small = max(i for i, b in enumerate(ex.batches) if any(rid != 0 for rid, _ in b))
+    assert first_big < last_small
