@@ -194,6 +194,9 @@ def parse():
     ap.add_argument("--loads", default="0.4,0.8,1.6",
                     help="offered loads, as fractions of the capacity measured by a saturation run")
     ap.add_argument("--grids", default="256,512,1024,2048", help="grid sizes of the serving requests")
+    ap.add_argument("--capacity", type=float, default=None,
+                    help="serving: requests/s measured by an earlier saturation run (skips the saturation run)")
+    ap.add_argument("--saturation-only", action="store_true", help="serving: only the saturation run")
     ap.add_argument("--no-serving", action="store_true",
                     help="leave the bounded serving leg (16 requests, one offered load) out of the default run")
     ap.add_argument("--precision-study", action="store_true",
@@ -265,7 +268,7 @@ def cpu_model():
     return None
 
 
-def serving_report(args, n_requests, grids, loads, seed=4, quiet=False):
+def serving_report(args, n_requests, grids, loads, seed=4, quiet=False, capacity=None, saturation_only=False):
     """Continuous-batching serving of a Poisson stream of mixed PRISM requests
     (`n_requests` requests of the stream seeded `seed`): a saturation run for
     the capacity, then one run per offered load (fraction of that capacity),
@@ -290,6 +293,8 @@ def serving_report(args, n_requests, grids, loads, seed=4, quiet=False):
             r = SV.Request(**p)
             r.sample = W.serving_sample(r.cell, r.seed)
             reqs.append(r)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
         log(f"[{tag}] serving {len(reqs)} requests at {rate:.3f}/s, budget {cap / 1e9:.1f} GB")
         ex = SV.GpuExecutor(prec, jobs_per_request=4)
         # batch cost: 2.5e12 complex multiply-adds, ~50 ms of split-BF16 contraction
@@ -301,9 +306,18 @@ def serving_report(args, n_requests, grids, loads, seed=4, quiet=False):
         torch.cuda.synchronize()
         return sched, time.perf_counter() - t0
 
-    # standalone capacity: every request present at t = 0 (saturation)
-    sat, sat_wall = run(0.0, "saturation")
-    capacity = len(sat.done) / sat_wall
+    # standalone capacity: every request present at t = 0 (saturation),
+    # unless the caller gives it (from an earlier saturation run)
+    sat_summary = None
+    if capacity is None:
+        sat, sat_wall = run(0.0, "saturation")
+        capacity = len(sat.done) / sat_wall
+        sat_summary = SV.summarize(sat, sat_wall)
+        if saturation_only:
+            return {"metric": "serving saturation run (all requests at t = 0)", "requests": sat_summary["requests"],
+                    "rejected": sat_summary["rejected"], "wall_s": sat_wall, "capacity_requests_per_s": capacity,
+                    "saturation_probes_per_s": sat_summary["probes_per_s"], "latency_by_grid": sat_summary["latency_by_grid"],
+                    "stream_seed": seed, "grids": list(grids), "data": "synthetic"}
     sweep = {}
     for ld in loads:
         sc, wl = run(ld * capacity, f"load {ld}")
@@ -344,7 +358,8 @@ def serving_report(args, n_requests, grids, loads, seed=4, quiet=False):
            "latency_by_grid": summ["latency_by_grid"], "stream_seed": seed,
            "requests": summ["requests"], "rejected": summ["rejected"], "probes": summ["probes"],
            "wall_s": wall, "arrival_rate_per_s": rate, "offered_load": ld0,
-           "capacity_requests_per_s": capacity, "saturation_probes_per_s": SV.summarize(sat, sat_wall)["probes_per_s"],
+           "capacity_requests_per_s": capacity,
+           "saturation_probes_per_s": sat_summary["probes_per_s"] if sat_summary else None,
            "load_sweep": {str(k): {"probes_per_s": v[2]["probes_per_s"], "p50_latency_s": v[2]["p50_latency_s"],
                                    "p99_latency_s": v[2]["p99_latency_s"], "wall_s": v[1],
                                    "latency_by_grid": v[2]["latency_by_grid"]}
@@ -364,7 +379,8 @@ def run_serving(args):
     """The serving benchmark alone (`--serve`)."""
     grids = tuple(int(x) for x in args.grids.split(","))
     loads = [float(x) for x in args.loads.split(",")]
-    print(json.dumps(serving_report(args, args.requests, grids, loads)), flush=True)
+    print(json.dumps(serving_report(args, args.requests, grids, loads, capacity=args.capacity,
+                                    saturation_only=args.saturation_only)), flush=True)
 
 
 def multislice_leg(args):

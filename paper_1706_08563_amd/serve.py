@@ -145,6 +145,19 @@ class Scheduler:
         self.building.extend(out)
         return out
 
+    def defer(self, req: Request):
+        """Return an admitted request whose device work could not start yet
+        (device memory held elsewhere) to the queue, in arrival order."""
+        if req in self.building:
+            self.building.remove(req)
+            self.used -= req.footprint
+        req.state = "queued"
+        req.t_admit = math.nan
+        k = 0
+        while k < len(self.queue) and self.queue[k].arrival <= req.arrival:
+            k += 1
+        self.queue.insert(k, req)
+
     def fail(self, req: Request, now: float, reason: str):
         """A request whose device work could not start (e.g. allocation failure)."""
         if req in self.building:
@@ -211,7 +224,8 @@ class GpuExecutor:
     """Runs requests with libprism on the current HIP device."""
 
     def __init__(self, precision: int, probe_chunk_bytes: int = 1 << 30, build_ws_bytes: int = 16 << 30,
-                 split_limit_bytes: int = 8 << 30, jobs_per_request: int = 4, range_pixels: int = 1 << 30):
+                 split_limit_bytes: int = 8 << 30, jobs_per_request: int = 4, range_pixels: int = 1 << 30,
+                 reserve_bytes: int = 8 << 30):
         import torch
 
         from . import api
@@ -227,6 +241,9 @@ class GpuExecutor:
         self.jobs_per_request = jobs_per_request      # must match the scheduler's
         # beams of one build range: about range_pixels beam-pixels (n^2 each)
         self.range_pixels = range_pixels
+        # device memory left free beside every request's footprint (the HIP
+        # runtime's own queues, scratch and events)
+        self.reserve_bytes = reserve_bytes
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
 
@@ -274,7 +291,17 @@ class GpuExecutor:
 
     # -- build --
     def start(self, req: Request):
+        """Allocate and issue the request's first build range; False when the
+        device does not have its footprint (plus the reserve) free.  The
+        scheduler's budget counts footprints only, while the caching
+        allocator keeps the blocks of finished requests: those are returned
+        to the device before the request is declared not to fit."""
         torch, api = self.torch, self.api
+        need = req.footprint + self.reserve_bytes
+        if torch.cuda.mem_get_info()[0] < need:
+            torch.cuda.empty_cache()
+            if torch.cuda.mem_get_info()[0] < need:
+                return False
         info = req.info
         d = info["desc"]
         st = torch.cuda.Stream()
@@ -290,6 +317,7 @@ class GpuExecutor:
         info["next_beam"] = 0
         info["built_event"] = None
         self._next_range(req)
+        return True
 
     def _next_range(self, req: Request):
         """Issue the request's next beam range on its stream."""
@@ -395,11 +423,19 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, idl
             req = pending[i]
             scheduler.arrive(req, executor.plan(req))
             i += 1
-        for req in scheduler.admit(now):
+        admitted = scheduler.admit(now)
+        for k, req in enumerate(admitted):
             try:
-                executor.start(req)
+                started = executor.start(req)
             except (MemoryError, RuntimeError) as exc:    # e.g. device allocation failure
                 scheduler.fail(req, clock() - t0, str(exc))
+                continue
+            if started is False:
+                # the device cannot hold it yet: it and the requests admitted
+                # after it wait in the queue
+                for r in admitted[k:]:
+                    scheduler.defer(r)
+                break
         for req in list(scheduler.building):
             if executor.is_built(req):
                 scheduler.mark_built(req, clock() - t0)

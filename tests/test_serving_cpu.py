@@ -186,3 +186,28 @@ def test_small_requests_are_batched_before_a_large_one_and_it_is_not_starved():
     first_big = min(i for i, b in enumerate(ex.batches) if any(rid == 0 for rid, _ in b))
     last_small = max(i for i, b in enumerate(ex.batches) if any(rid != 0 for rid, _ in b))
     assert first_big < last_small
+
+
+def test_request_that_cannot_start_waits_and_budget_is_released():
+    """An admitted request whose device memory is not free yet goes back to
+    the queue (budget released) and starts later; nothing is lost."""
+    class Refusing(FakeExecutor):
+        def __init__(self, clock):
+            super().__init__(clock)
+            self.refused = 0
+
+        def start(self, req):
+            if req.rid == 1 and self.refused < 3:
+                self.refused += 1
+                return False
+            super().start(req)
+            return True
+
+    reqs = [_req(i, 0.0, foot=30) for i in range(4)]
+    clk = Clock()
+    ex = Refusing(clk)
+    sched = Scheduler(100, max_building=4)
+    serve(reqs, ex, sched, clock=clk, sleep=clk.sleep)
+    assert ex.refused == 3
+    assert {r.rid for r in sched.done} == {0, 1, 2, 3} and not sched.rejected
+    assert sched.used == 0 and sched.peak_used <= 100
