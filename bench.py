@@ -302,7 +302,7 @@ def serving_report(args, n_requests, grids, loads, seed=4, quiet=False, capacity
         t0 = time.perf_counter()
         SV.serve(reqs, ex, sched, on_done=None if quiet else
                  lambda r: log(f"  [{tag}] done {r.rid} n={r.n} f={r.f} S={r.n_slices} P={r.n_probes} "
-                               f"latency {r.latency:.2f} s"))
+                               f"latency {r.latency:.2f} s, device free {torch.cuda.mem_get_info()[0] / 1e9:.0f} GB"))
         torch.cuda.synchronize()
         return sched, time.perf_counter() - t0
 

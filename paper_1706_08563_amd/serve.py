@@ -244,6 +244,8 @@ class GpuExecutor:
         # device memory left free beside every request's footprint (the HIP
         # runtime's own queues, scratch and events)
         self.reserve_bytes = reserve_bytes
+        # requests above this footprint return their cached blocks when done
+        self.release_bytes = 16 << 30
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
 
@@ -396,6 +398,10 @@ class GpuExecutor:
         req.result = info["out"].cpu().numpy()
         for k in ("S", "out", "plans"):
             info.pop(k, None)
+        if req.footprint > self.release_bytes:
+            # return a large request's blocks to the device at once, so that
+            # the next large request finds them free rather than cached
+            self.torch.cuda.empty_cache()
 
     def chunks_left(self, req: Request):
         return range(req.chunks_issued, req.chunks_total)
