@@ -240,3 +240,21 @@ def test_detector_map_plans_and_validation():
         == P.PRISM_E_INVAL
     assert P.lib.prism_probe_plan_upload(ct.byref(d), xyc.ctypes.data_as(ct.c_void_p), ct.byref(p), fake, None) \
         == P.PRISM_E_INVAL
+
+
+def test_build_range_argument_checks():
+    """prism_build_smatrix_range refuses ranges outside [0, n_beams) and a
+    short workspace before any device work (fake device pointers)."""
+    P = _lib()
+    w = W.WORKLOADS["prism_f2_sc_256"]
+    g = P.prism_grid_init(w.cell, w.dz, w.n)
+    d = P.prism_smatrix_plan(g, w.E0, w.alpha_max, w.f)
+    ct = P._lib.ctypes
+    fake = ct.c_void_p(256)
+    for first, cnt in ((-1, 1), (0, -1), (0, d.n_beams + 1), (d.n_beams, 1), (d.n_beams - 3, 4)):
+        rc = P.lib.prism_build_smatrix_range(ct.byref(d), fake, fake, first, cnt, fake, d.build_ws_bytes, None)
+        assert rc == P.PRISM_E_INVAL, (first, cnt)
+    rc = P.lib.prism_build_smatrix_range(ct.byref(d), fake, fake, 0, 1, fake, d.build_ws_bytes - 1, None)
+    assert rc == P.PRISM_E_WORKSPACE
+    # an empty range is accepted and does nothing
+    assert P.lib.prism_build_smatrix_range(ct.byref(d), fake, fake, 5, 0, fake, d.build_ws_bytes, None) == P.PRISM_OK
