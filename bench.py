@@ -256,6 +256,14 @@ def cpu_baseline(w, d, n_beams, n_probes, args):
             "beams_per_s": 1.0 / t_beam}
 
 
+def device_info():
+    """Name, architecture, compute units and memory of the benchmarked GPU."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "memory_GB": p.total_memory / 1e9}
+
+
 def cpu_model():
     """The host CPU's model name (first processor in /proc/cpuinfo)."""
     try:
@@ -758,6 +766,7 @@ def main():
         "kernels": kernels,
         "roofline": roof,
         "hbm_copy_GB_per_s": copy_bandwidth(),
+        "device": device_info(),
     }
     res["multislice"], ms_out = multislice_leg(args)
     if w.name == "prism_f4_np_1024":
