@@ -59,6 +59,7 @@ class Request:
     chunks_issued: int = 0
     chunk_cost: float = 1.0        # synthesis work of one probe chunk (any unit, set by the executor)
     passed: int = 0                # batches formed without this request while it had chunks left
+    held_since: float = math.nan   # when its build was first held back behind smaller builds
     t_admit: float = math.nan
     t_built: float = math.nan
     t_done: float = math.nan
@@ -84,7 +85,8 @@ class Scheduler:
     """Admission, bookkeeping and batch formation; no device state."""
 
     def __init__(self, capacity: int, max_building: int = 4, max_jobs: int = 24, aging: int = 8,
-                 jobs_per_request: int = 4, batch_cost: float | None = None):
+                 jobs_per_request: int = 4, batch_cost: float | None = None, build_ratio: float = math.inf,
+                 build_hold: float = 2.0):
         self.capacity = int(capacity)
         self.used = 0
         self.max_building = max_building
@@ -96,6 +98,14 @@ class Scheduler:
         # a batch takes further chunks only while its summed chunk_cost stays
         # within this (None: no limit)
         self.batch_cost = batch_cost
+        # a build whose remaining work exceeds build_ratio x the smallest
+        # remaining build issues no further part until the smaller ones are
+        # done, or until it has been held build_hold seconds (inf: builds are
+        # never held; on mixed streams of 256^2-2048^2 grids at load 0.8 a
+        # ratio of 4 lowered the median latency but raised the 99th
+        # percentile by about 2 % at the same throughput)
+        self.build_ratio = build_ratio
+        self.build_hold = build_hold
         self.queue: list[Request] = []
         self.building: list[Request] = []
         self.built: list[Request] = []
@@ -167,6 +177,20 @@ class Scheduler:
         req.t_done = now
         req.info["error"] = reason
         self.rejected.append(req)
+
+    def may_build(self, req: Request, now: float, build_left) -> bool:
+        """Whether a building request may issue the next part of its build:
+        smaller builds go first (`build_left(req)` is its remaining work)."""
+        smallest = min(build_left(r) for r in self.building)
+        if build_left(req) <= self.build_ratio * smallest:
+            req.held_since = math.nan
+            return True
+        if math.isnan(req.held_since):
+            req.held_since = now
+        if now - req.held_since >= self.build_hold:
+            req.held_since = math.nan
+            return True
+        return False
 
     def mark_built(self, req: Request, now: float):
         self.building.remove(req)
@@ -341,16 +365,22 @@ class GpuExecutor:
                 info[k].record_stream(st)
                 del info[k]
 
-    def is_built(self, req: Request) -> bool:
+    def is_built(self, req: Request, may_issue: bool = True) -> bool:
         """True once every range has finished; issues the next range when the
-        previous one has."""
+        previous one has (and the scheduler lets it)."""
         info = req.info
         if not info["built_event"].query():
             return False
         if info["next_beam"] < info["desc"].n_beams:
-            self._next_range(req)
+            if may_issue:
+                self._next_range(req)
             return False
         return True
+
+    def build_left(self, req: Request) -> float:
+        """Remaining build work of a request: beams not yet issued x slices x n^2."""
+        info = req.info
+        return float(info["desc"].n_beams - info["next_beam"]) * req.n_slices * req.n * req.n
 
     # -- synthesis --
     def synthesize(self, batch):
@@ -442,8 +472,13 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, idl
                 for r in admitted[k:]:
                     scheduler.defer(r)
                 break
+        build_left = getattr(executor, "build_left", None) if math.isfinite(scheduler.build_ratio) else None
         for req in list(scheduler.building):
-            if executor.is_built(req):
+            if build_left is None:
+                built = executor.is_built(req)
+            else:
+                built = executor.is_built(req, scheduler.may_build(req, clock() - t0, build_left))
+            if built:
                 scheduler.mark_built(req, clock() - t0)
         if not executor.inflight:
             batch = scheduler.next_batch(executor.chunks_left)

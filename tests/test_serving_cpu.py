@@ -211,3 +211,67 @@ def test_request_that_cannot_start_waits_and_budget_is_released():
     assert ex.refused == 3
     assert {r.rid for r in sched.done} == {0, 1, 2, 3} and not sched.rejected
     assert sched.used == 0 and sched.peak_used <= 100
+
+
+def test_smaller_builds_go_first_and_large_ones_are_not_held_forever():
+    """A build with much more work left than the smallest one waits, until it
+    has been held build_hold seconds; builds within build_ratio proceed."""
+    sched = Scheduler(1000, build_ratio=4.0, build_hold=2.0)
+    big, small, mid = _req(0, 0.0, 10), _req(1, 0.0, 10), _req(2, 0.0, 10)
+    left = {0: 1000.0, 1: 10.0, 2: 30.0}
+    sched.building = [big, small, mid]
+    f = lambda r: left[r.rid]            # noqa: E731
+    assert sched.may_build(small, 0.0, f) and sched.may_build(mid, 0.0, f)
+    assert not sched.may_build(big, 0.0, f) and not sched.may_build(big, 1.9, f)
+    assert sched.may_build(big, 2.0, f)          # held long enough
+    assert not sched.may_build(big, 2.5, f)      # and held again from now on
+    sched.building = [big]
+    assert sched.may_build(big, 2.6, f)          # alone: nothing smaller to wait for
+
+
+class RangedExecutor(FakeExecutor):
+    """Builds in parts of 1 ms each on one serial build queue; the next part
+    of a request is issued only after its previous part has finished."""
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.busy_until = 0.0
+
+    def _issue(self, req):
+        start = max(self.clock(), self.busy_until)
+        self.busy_until = start + 1e-3
+        req.info["part_done"] = self.busy_until
+        req.info["parts_left"] -= 1
+
+    def start(self, req):
+        req.info["parts_left"] = req.info["parts"]
+        self._issue(req)
+
+    def is_built(self, req, may_issue=True):
+        if self.clock() < req.info["part_done"]:
+            return False
+        if req.info["parts_left"]:
+            if may_issue:
+                self._issue(req)
+            return False
+        return True
+
+    def build_left(self, req):
+        return float(req.info["parts_left"])
+
+
+def test_build_pacing_in_the_serving_loop():
+    """With pacing, a small build admitted beside a large one is built on
+    its own; without it the two interleave part by part.  Both finish."""
+    def run(**kw):
+        clk = Clock()
+        big, small = _req(0, 0.0, 10), _req(1, 0.0055, 10)
+        big.info["parts"], small.info["parts"] = 40, 3
+        sched = Scheduler(1000, **kw)
+        serve([big, small], RangedExecutor(clk), sched, clock=clk, sleep=clk.sleep)
+        assert {r.rid for r in sched.done} == {0, 1}
+        return big.t_built, small.t_built - small.t_admit
+    big_free, small_free = run()
+    big_paced, small_paced = run(build_ratio=4.0, build_hold=1.0)
+    assert small_paced < small_free
+    assert big_paced >= big_free
