@@ -30,6 +30,9 @@ constexpr int WG = 256;      // 4 wavefronts
 #ifndef PRISM_PASSA_ROWS
 #define PRISM_PASSA_ROWS 16      // rows per pass-A workgroup for n <= 1024 (half that above)
 #endif
+#ifndef PRISM_PASSA_PAIR
+#define PRISM_PASSA_PAIR 0       // 1: the two row tiles of one 2*TR-row band segment run on one XCD together
+#endif
 #ifndef PRISM_PASSA_ILP
 #define PRISM_PASSA_ILP 0        // 1: even/odd row transforms advanced together (extra LDS)
 #endif
@@ -174,8 +177,29 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
     float2* const tile = smem;
     float2* const xodd = smem + TR * ROW;
 
-    const int item = blk % n_items;
-    const int y0 = (blk / n_items) * TR;
+    int item, y0;
+    if constexpr (PRISM_PASSA_PAIR && (N / TR) % 2 == 0) {
+        // Workgroups are dealt to the 8 XCDs in turn (blk % 8), so blocks blk
+        // and blk + 8 of a run of 16 share an XCD and start together: give
+        // them the two row tiles whose column segments share 2*TR*8-byte
+        // lines.  Units (pairs of tiles) run item-fastest, as the tiles do
+        // without pairing; a tail of fewer than 16 blocks takes its units two
+        // blocks at a time.
+        const int grid = n_items * (N / TR), full = grid & ~15;
+        int u, h;
+        if (blk < full) {
+            u = (blk >> 4) * 8 + (blk & 7);
+            h = (blk >> 3) & 1;
+        } else {
+            u = (full >> 1) + ((blk - full) >> 1);
+            h = (blk - full) & 1;
+        }
+        item = u % n_items;
+        y0 = (2 * (u / n_items) + h) * TR;
+    } else {
+        item = blk % n_items;
+        y0 = (blk / n_items) * TR;
+    }
     constexpr int CS = wave_col_stride(N);
     float2* Wi = W + (size_t)item * L * CS;
     const int tid = threadIdx.x;
