@@ -181,8 +181,10 @@ class Scheduler:
     def may_build(self, req: Request, now: float, build_left) -> bool:
         """Whether a building request may issue the next part of its build:
         smaller builds go first (`build_left(req)` is its remaining work)."""
-        smallest = min(build_left(r) for r in self.building)
-        if build_left(req) <= self.build_ratio * smallest:
+        mine = build_left(req)
+        # builds whose every part is issued hold nobody back
+        smallest = min((x for x in (build_left(r) for r in self.building) if x > 0), default=0.0)
+        if mine <= 0 or mine <= self.build_ratio * smallest:
             req.held_since = math.nan
             return True
         if math.isnan(req.held_since):
@@ -279,7 +281,7 @@ class GpuExecutor:
         api = self.api
         g = api.prism_grid_init(req.cell, 2.0, req.n)
         d = api.prism_smatrix_plan(g, req.E0, req.alpha_max, req.f)
-        per_beam = (d.build_ws_bytes - 0) // max(d.n_beams, 1)
+        per_beam = d.build_ws_bytes // max(d.n_beams, 1)
         bb = max(1, min(d.n_beams, self.build_ws_bytes // max(per_beam, 1)))
         if bb < d.n_beams:
             d = api.prism_smatrix_plan(g, req.E0, req.alpha_max, req.f, beam_batch=bb)

@@ -227,6 +227,9 @@ def test_smaller_builds_go_first_and_large_ones_are_not_held_forever():
     assert not sched.may_build(big, 2.5, f)      # and held again from now on
     sched.building = [big]
     assert sched.may_build(big, 2.6, f)          # alone: nothing smaller to wait for
+    left[1] = 0.0                                # a build with every part issued
+    sched.building = [big, small]
+    assert sched.may_build(big, 2.7, f) and sched.may_build(small, 2.7, f)
 
 
 class RangedExecutor(FakeExecutor):
