@@ -100,3 +100,17 @@ def test_builds_in_beam_ranges_equal_whole_builds():
     for x, y in zip(a, b):
         say(f"  request {x.rid} (n={x.n}, {x.info['n_beams']} beams, ranges of {x.info['range_beams']})")
         assert np.array_equal(x.result, y.result)
+
+
+def test_paced_builds_equal_unpaced():
+    """With build pacing on (larger builds hold their next range while
+    smaller ones proceed) every request completes and its result equals the
+    unpaced run bit for bit."""
+    say("serving: build pacing on vs off, builds in small beam ranges")
+    a = _requests()
+    sched = _run(a, 1, max_building=4, max_jobs=8, range_pixels=16 * 128 * 128, build_ratio=2.0, build_hold=0.5)
+    assert len(sched.done) == len(a) and not sched.rejected
+    b = _requests()
+    _run(b, 1, max_building=4, max_jobs=8, range_pixels=16 * 128 * 128)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.result, y.result), f"request {x.rid}"
