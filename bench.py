@@ -658,9 +658,10 @@ def main():
         return (wall_s, [a.elapsed_time(c) for a, b, c in ev], [a.elapsed_time(b) for a, b, c in ev],
                 [b.elapsed_time(c) for a, b, c in ev])
 
-    # headline: the build overlaps its two beam halves on two streams
+    # headline: the library's default build streams (two overlapping beam
+    # halves up to 1024^2, one stream above)
     log(f"timed {args.steps} steps")
-    P.prism_set_build_streams(2)
+    P.prism_set_build_streams(0)
     wall, step_ms, build_ms, synth_ms = run_steps(args.steps, False)
     log(f"steps done: wall {wall:.3f} s; step ms {step_ms}")
     # per-kernel times (roofline): one stream, so that launches do not overlap
@@ -668,7 +669,7 @@ def main():
     log(f"kernel timing: {k_steps} one-stream steps")
     P.prism_set_build_streams(1)
     _, _, build_ms_1, _ = run_steps(k_steps, True)
-    P.prism_set_build_streams(2)
+    P.prism_set_build_streams(0)
     kt = {name: P.prism_timing_read(cls) for name, cls in P.TIMING_CLASSES.items()}
     # end to end with the probe planning in every step: the host plans the
     # scan and uploads its tables on a side stream while the GPU builds the
@@ -757,6 +758,7 @@ def main():
         "p99_ms": float(np.percentile(step_ms, 99)),
         "build_ms": float(np.median(build_ms)),
         "build_ms_one_stream": float(np.median(build_ms_1)),
+        "build_streams": 2 if n <= 1024 else 1,
         "synthesis_ms": float(np.median(synth_ms)),
         "probe_plan_host_s": plan_s,
         # whole steps that also plan the scan (window corners, work tiles,

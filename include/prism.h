@@ -182,8 +182,10 @@ int prism_build_smatrix(const prism_smatrix_desc* d, const float* V, void* S,
 int prism_build_smatrix_range(const prism_smatrix_desc* d, const float* V, void* S, int32_t first,
                               int32_t count, void* ws, size_t ws_bytes, void* stream);
 
-/* Streams used by prism_build_smatrix (process-wide), n in 1..4 (default 2):
- * every beam batch is split into n parts, run on `stream` and on n - 1
+/* Streams used by prism_build_smatrix (process-wide), n in 1..4, or 0 (the
+ * default) for a count chosen by grid size: 2 for n <= 1024, 1 above, where
+ * the row and column passes of 1024-point transforms gain nothing from
+ * running together.  Every beam batch is split into n parts, run on `stream` and on n - 1
  * partner streams that the library creates once per caller stream (default
  * priority, kept until the process ends), each part one row pass behind the
  * previous one, so that row and column passes of different beams run
@@ -192,7 +194,7 @@ int prism_build_smatrix_range(const prism_smatrix_desc* d, const float* V, void*
  * fewer than n beams use as many streams as beams.  At most 32 caller
  * streams get partners; builds on any further caller stream run on that
  * stream alone.
- * Errors: PRISM_E_INVAL (n outside 1..4). */
+ * Errors: PRISM_E_INVAL (n outside 0..4). */
 int prism_set_build_streams(int32_t n);
 
 /* ---- PRISM probe outputs (Fig. 1i-k) -------------------------------------- */

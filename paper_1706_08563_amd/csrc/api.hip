@@ -697,7 +697,15 @@ int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap) {
 // issue) of one part share the GPU with column passes (bound by memory
 // latency) of another, each kernel at its own occupancy.
 constexpr int kMaxBuildStreams = 4;
-std::atomic<int> g_build_streams{2};
+// 0: by grid size.  Two streams up to n = 1024 (1245 beams at 1024^2: 266 ->
+// 259 ms per build); one above, where a row pass and a column pass of
+// 1024-point transforms compete for the same LDS (1245 beams at 2048^2:
+// 1.505 s on two streams against 1.494 s on one).
+std::atomic<int> g_build_streams{0};
+int build_streams_for(int n) {
+    const int s = g_build_streams.load();
+    return s > 0 ? s : (n <= 1024 ? 2 : 1);
+}
 std::mutex g_partner_mu;
 std::map<hipStream_t, std::vector<hipStream_t>> g_partner;
 
@@ -731,7 +739,8 @@ struct BuildEvents {
 };
 
 int prism_set_build_streams(int32_t n) {
-    if (n < 1 || n > kMaxBuildStreams) return fail(PRISM_E_INVAL, "build streams must be 1 to %d", kMaxBuildStreams);
+    if (n < 0 || n > kMaxBuildStreams)
+        return fail(PRISM_E_INVAL, "build streams must be 1 to %d (0: by grid size)", kMaxBuildStreams);
     g_build_streams.store(n);
     return PRISM_OK;
 }
@@ -786,7 +795,7 @@ static int build_range(const prism_smatrix_desc* d, const float* V, void* S, int
         HIP_TRY(timed(PRISM_K_FINAL, q, [&] { return launch_smatrix_final(n, Wq, Sq, pd.tw_half, cnt, q); }));
         return PRISM_OK;
     };
-    int P = std::min(g_build_streams.load(), NB);
+    int P = std::min(build_streams_for(n), NB);
     hipStream_t q[kMaxBuildStreams] = {st};
     if (P > 1) {
         int got = 0;

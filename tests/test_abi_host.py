@@ -187,11 +187,11 @@ def test_one_hip_runtime_whatever_the_import_order():
 
 def test_build_stream_count_validation():
     import paper_1706_08563_amd as P
-    for bad in (0, 5, -1):
+    for bad in (5, -1):
         with pytest.raises(P.PrismError) as e:
             P.prism_set_build_streams(bad)
         assert e.value.code == P.PRISM_E_INVAL
-    for ok in (1, 3, 4, 2):                           # ends on the default
+    for ok in (1, 3, 4, 2, 0):                        # ends on the default (by grid size)
         P.prism_set_build_streams(ok)
 
 

@@ -391,7 +391,7 @@ def test_multi_stream_build_equals_one_stream(P, streams, beam_batch):
             S3 = P.prism_build_smatrix(d, V)
         torch.cuda.synchronize()
     finally:
-        P.prism_set_build_streams(2)
+        P.prism_set_build_streams(0)
     a = S1.cpu().numpy()
     assert np.array_equal(a, S2.cpu().numpy()) and np.array_equal(a, S3.cpu().numpy())
     Vref = O.projected_potential(pos, sp, w.species, w.cell, w.dz, w.n)
@@ -425,7 +425,7 @@ def test_build_in_beam_ranges_equals_whole_build(P, streams, beam_batch, ranges)
             b0 += cnt
         torch.cuda.synchronize()
     finally:
-        P.prism_set_build_streams(2)
+        P.prism_set_build_streams(0)
     a, b = whole.cpu().numpy(), S.cpu().numpy()
     assert np.array_equal(a[:b0], b[:b0])
     assert np.all(b[b0:] == np.complex64(complex(7.0, -3.0)))
