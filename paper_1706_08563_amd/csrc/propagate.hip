@@ -498,14 +498,16 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PRISM_PASSB_
     pass_b_block<N, MODE>(W, tb, aux, inten, ky_max, probe_xy, inv_L, amp, n_items, blockIdx.x, smem);
 }
 
-// Tile-staged column pass for interior slices (used from n = 2048, one
-// transform per wavefront pair there): a workgroup stages TC whole columns
-// into LDS with all its loads in flight at once (as pass A stages its row
-// tile), then the wavefronts transform the columns from LDS, using each
+// Tile-staged column pass for interior and last slices (used from n = 2048,
+// one transform per wavefront pair there): a workgroup stages TC whole
+// columns into LDS with all its loads in flight at once (as pass A stages its
+// row tile), then the wavefronts transform the columns from LDS, using each
 // column's own LDS slots as the two padded exchange buffers of its even and
-// odd transforms, and write the result straight from registers.
+// odd transforms, and write the result straight from registers.  The last
+// slice of an S-matrix build writes the even rows only; that of a multislice
+// run writes the band intensities.
 #ifndef PRISM_PASSB_TILE_MIN
-#define PRISM_PASSB_TILE_MIN 2048   // smallest n whose interior column passes use k_pass_b_tile
+#define PRISM_PASSB_TILE_MIN 2048   // smallest n whose column passes (all but the first) use k_pass_b_tile
 #endif
 template <int N>
 struct PassBTile {
@@ -518,8 +520,10 @@ struct PassBTile {
     static constexpr int TPW = WG / F::LPT;                   // columns transformed at once
 };
 
-template <int N>
-__global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, PropTables tb, int n_items) {
+template <int N, int MODE>
+__global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, PropTables tb, float* __restrict__ inten,
+                                                    int n_items) {
+    static_assert(MODE == PASSB_MID || MODE == PASSB_LAST_S || MODE == PASSB_LAST_I, "interior or last slice");
     using T = PassBTile<N>;
     using F = typename T::F;
     constexpr int L = N / 2, E = F::E, LPT = F::LPT, TC = T::TC, CS = T::CS, TPW = T::TPW;
@@ -578,13 +582,29 @@ __global__ __launch_bounds__(WG) void k_pass_b_tile(float2* __restrict__ W, Prop
             const float2 psi = cadd(e[i], cmul(btw[i], o[i]));
             const bool in = 16 * (kxj * kxj + ky * ky) < N * N;
             e[i] = in ? cmul(psi, cmul(pj, pk[i])) : make_float2(0.f, 0.f);
-            o[i] = cmulc(e[i], btw[i]);
         }
-        F::template run<+1>(e, xe, tw, lt);
-        F::template run<+1>(o, xo, tw, lt);
-        float4* col4 = reinterpret_cast<float4*>(Wi + (size_t)j * wave_col_stride(N));
+        if constexpr (MODE == PASSB_LAST_I) {
+            // multislice exit: band intensities of this column
+            float* dst = inten + ((size_t)item * L + j) * L;
 #pragma unroll
-        for (int i = 0; i < E; ++i) wave_store<PRISM_NT_BS>(col4 + lt + LPT * i, make_float4(e[i].x, e[i].y, o[i].x, o[i].y));
+            for (int i = 0; i < E; ++i) dst[lt + LPT * i] = cnorm(e[i]);
+        } else if constexpr (MODE == PASSB_LAST_S) {
+            // S-matrix exit: even rows only, psi(2 my) for my in [0, n/2),
+            // over the first half of this (already staged) column
+            F::template run<+1>(e, xe, tw, lt);
+            float2* col = Wi + (size_t)j * wave_col_stride(N);
+#pragma unroll
+            for (int i = 0; i < E; ++i) col[lt + LPT * i] = e[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) o[i] = cmulc(e[i], btw[i]);
+            F::template run<+1>(e, xe, tw, lt);
+            F::template run<+1>(o, xo, tw, lt);
+            float4* col4 = reinterpret_cast<float4*>(Wi + (size_t)j * wave_col_stride(N));
+#pragma unroll
+            for (int i = 0; i < E; ++i)
+                wave_store<PRISM_NT_BS>(col4 + lt + LPT * i, make_float4(e[i].x, e[i].y, o[i].x, o[i].y));
+        }
     }
 }
 
@@ -592,11 +612,11 @@ template <int N, int MODE>
 static hipError_t pass_b_nm(float2* W, const PropTables& tb, const float2* aux, float* inten, const int* ky_max,
                             const double2* xy, double inv_L, float amp, int n_items, hipStream_t st) {
     constexpr int L = N / 2, LPT = Fft<L>::LPT, CPB = 4 * (64 / LPT) * PassBCols<N, MODE>::value;
-    if constexpr (MODE == PASSB_MID && PassBTile<N>::ok) {
+    if constexpr (MODE != PASSB_INIT && PassBTile<N>::ok) {
         constexpr int TC = PassBTile<N>::TC;
         static_assert(L % TC == 0, "columns must split into whole tiles");
         dim3 grid((unsigned)((size_t)n_items * (L / TC)));
-        hipLaunchKernelGGL((k_pass_b_tile<N>), grid, dim3(WG), 0, st, W, tb, n_items);
+        hipLaunchKernelGGL((k_pass_b_tile<N, MODE>), grid, dim3(WG), 0, st, W, tb, inten, n_items);
         return hipGetLastError();
     }
     dim3 grid((unsigned)((size_t)n_items * ((L + CPB - 1) / CPB)));
