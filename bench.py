@@ -548,7 +548,8 @@ def streaming_study(args):
 def pmc_driver(args):
     """One launch of every kernel of the default workload at its real per-launch
     size (the build cut to 4 slices, on one stream as in the per-kernel timing:
-    one first-slice and three interior launches of each pass over all beams),
+    the first-slice gather, three interior row passes and four column passes
+    over all beams),
     then a plain 256 MiB copy whose byte count calibrates the FETCH_SIZE /
     WRITE_SIZE counters."""
     import dataclasses
@@ -693,8 +694,10 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     N2 = float(n) * n
     # algorithmic HBM bytes per launch of the propagation passes (band-limited
-    # wave: 4 N^2 B per beam read and written, plus the slice's transmission)
-    a_bytes = (B * 8 * N2 * (nsl - 1) + B * 4 * N2 + nsl * 8 * N2) / nsl
+    # wave: 4 N^2 B per beam read and written, plus the slice's transmission;
+    # the row pass runs on slices 2..S, the first slice being a gather from
+    # the row spectrum, timed as "first")
+    a_bytes = B * 8 * N2 + 8 * N2
     b_bytes = (B * 8 * N2 * (nsl - 1) + B * 6 * N2) / nsl
     c_flops = 8.0 * B * M * M * n_probes          # useful complex MACs x 8
     kernels = {}

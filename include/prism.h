@@ -187,7 +187,7 @@ int prism_build_smatrix_range(const prism_smatrix_desc* d, const float* V, void*
  * the row and column passes of 1024-point transforms gain nothing from
  * running together.  Every beam batch is split into n parts, run on `stream` and on n - 1
  * partner streams that the library creates once per caller stream (default
- * priority, kept until the process ends), each part one row pass behind the
+ * priority, kept until the process ends), each part one slice behind the
  * previous one, so that row and column passes of different beams run
  * together.  The call still returns with all work ordered on `stream`, and
  * the S-matrix is identical to the one-stream build (n = 1).  Batches of
@@ -442,14 +442,15 @@ int prism_detector_default_bins(const prism_grid* grid, double E0, double dalpha
 #define PRISM_K_PASS_A         0   /* row pass: inverse row DFT, transmission, forward row DFT */
 #define PRISM_K_PASS_B         1   /* column pass: forward column DFT, propagator, inverse column DFT */
 #define PRISM_K_FINAL          2   /* S-matrix real-space store */
-#define PRISM_K_TRANSMISSION   3   /* exp(i sigma V) */
+#define PRISM_K_TRANSMISSION   3   /* exp(i sigma V); also the first slice's row spectrum */
 #define PRISM_K_COEFFICIENTS   4   /* probe coefficients */
 #define PRISM_K_CONTRACT       5   /* windowed beam contraction */
 #define PRISM_K_WINDOW         6   /* window FFT, |Psi|^2, detector sums */
 #define PRISM_K_POTENTIAL      7   /* projected potential */
 #define PRISM_K_BIN_REDUCE     8   /* multislice detector sums */
 #define PRISM_K_SPLIT          9   /* S-matrix to split-BF16 records (MFMA precisions) */
-#define PRISM_TIMING_CLASSES  10
+#define PRISM_K_FIRST         10   /* first slice of an S-matrix build (plane waves from the row spectrum) */
+#define PRISM_TIMING_CLASSES  11
 
 /* While enabled (per calling thread), every kernel launch of the library is
  * bracketed by HIP events recorded on its stream. */

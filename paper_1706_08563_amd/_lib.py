@@ -129,7 +129,7 @@ _SIGNATURES = {
 }
 
 TIMING_CLASSES = {"pass_a": 0, "pass_b": 1, "final": 2, "transmission": 3, "coefficients": 4, "contract": 5,
-                  "window": 6, "potential": 7, "bin_reduce": 8, "split": 9}
+                  "window": 6, "potential": 7, "bin_reduce": 8, "split": 9, "first": 10}
 
 EXPORTED = tuple(_SIGNATURES)
 

@@ -672,6 +672,7 @@ int prism_smatrix_plan(prism_smatrix_desc* d) {
     carve_prop(c, n);
     c.take<int2>(d->n_beams);
     c.take<float2>((size_t)d->grid.n_slices * n * n);
+    c.take<float2>((size_t)n * n);                           // row spectrum of the first slice
     c.take<float2>((size_t)batch_of(d) * (n / 2) * wave_col_stride(n));
     d->build_ws_bytes = c.off + 256;
     return PRISM_OK;
@@ -693,10 +694,17 @@ int prism_beam_list(const prism_smatrix_desc* d, int32_t* k_out, int32_t cap) {
 // The S-matrix build splits each beam batch into parts, one per stream: the
 // caller's stream and up to three partner streams (created once per caller
 // stream, default priority, kept for the life of the process).  Stream k
-// starts one row pass after stream k-1, so that row passes (bound by VALU
-// issue) of one part share the GPU with column passes (bound by memory
-// latency) of another, each kernel at its own occupancy.
+// starts after the first slice of stream k-1 (its plane-wave gather and
+// first column pass), so that row passes (bound by VALU issue) of one part
+// share the GPU with column passes (bound by memory latency) of another,
+// each kernel at its own occupancy.
 constexpr int kMaxBuildStreams = 4;
+// Part k starts after part k-1's first row pass (0), first column pass (1)
+// or second row pass (2): 1245 beams at 1024^2 on two streams took 261.1,
+// 256.5 and 261.5 ms per build.
+#ifndef PRISM_FORK_STAGE
+#define PRISM_FORK_STAGE 1
+#endif
 // 0: by grid size.  Two streams up to n = 1024 (1245 beams at 1024^2: 266 ->
 // 259 ms per build); one above, where a row pass and a column pass of
 // 1024-point transforms compete for the same LDS (1245 beams at 2048^2:
@@ -765,6 +773,7 @@ static int build_range(const prism_smatrix_desc* d, const float* V, void* S, int
     PropDev pd = carve_prop(c, n);
     int2* d_beams = c.take<int2>(B);
     float2* T = c.take<float2>((size_t)nsl * n * n);
+    float2* R0 = c.take<float2>((size_t)n * n);
     float2* W = c.take<float2>((size_t)NB * (n / 2) * wave_col_stride(n));
     PropHost ph = prop_tables(n, L, d->lambda, d->grid.dz);
     std::vector<char> blob;
@@ -777,6 +786,7 @@ static int build_range(const prism_smatrix_desc* d, const float* V, void* S, int
     if (rc) return rc;
     const PropTables tb = pd.tables();
     HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_transmission(V, T, (int64_t)nsl * n * n, (float)d->sigma, st); }));
+    HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_row_spectrum(n, T, R0, tb, st); }));
     float2* Sout = static_cast<float2*>(S);
     const size_t item_w = (size_t)(n / 2) * wave_col_stride(n), layer = (size_t)(n / 2) * (n / 2);
     // items [i0, i0 + cnt) of the batch starting at beam b0, all slices then the store, on stream q
@@ -784,12 +794,18 @@ static int build_range(const prism_smatrix_desc* d, const float* V, void* S, int
         float2* Wq = W + (size_t)i0 * item_w;
         const int2* bq = d_beams + b0 + i0;
         for (int s = 0; s < nsl; ++s) {
-            HIP_TRY(timed(PRISM_K_PASS_A, q, [&] { return launch_pass_a(n, Wq, T + (size_t)s * n * n, tb, bq, s == 0, cnt, q); }));
-            if (s == 0 && after_first_a) HIP_TRY(hipEventRecord(after_first_a, q));
+            if (s == 0)
+                HIP_TRY(timed(PRISM_K_FIRST, q, [&] { return launch_first_from_spectrum(n, Wq, R0, tb, bq, cnt, q); }));
+            else
+                HIP_TRY(timed(PRISM_K_PASS_A, q, [&] { return launch_pass_a(n, Wq, T + (size_t)s * n * n, tb, cnt, q); }));
+            if (PRISM_FORK_STAGE == 0 && s == 0 && after_first_a) HIP_TRY(hipEventRecord(after_first_a, q));
+            if (PRISM_FORK_STAGE == 2 && s == std::min(1, nsl - 1) && after_first_a)
+                HIP_TRY(hipEventRecord(after_first_a, q));
             HIP_TRY(timed(PRISM_K_PASS_B, q, [&] {
                 return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, Wq, tb, nullptr, nullptr, nullptr,
                                      nullptr, 0.0, 0.f, cnt, q);
             }));
+            if (PRISM_FORK_STAGE == 1 && s == 0 && after_first_a) HIP_TRY(hipEventRecord(after_first_a, q));
         }
         float2* Sq = Sout + (size_t)(b0 + i0) * layer;
         HIP_TRY(timed(PRISM_K_FINAL, q, [&] { return launch_smatrix_final(n, Wq, Sq, pd.tw_half, cnt, q); }));
@@ -1415,7 +1431,7 @@ static int multislice_run(const prism_grid* grid, double E0, double alpha_max, c
                 if (rc) return rc;
                 Ts = m.T;
             }
-            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, m.W, Ts, tb, nullptr, false, nb, st); }));
+            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, m.W, Ts, tb, nb, st); }));
             HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
                 return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_I : PASSB_MID, m.W, tb, nullptr, m.I, nullptr,
                                      nullptr, 0.0, 0.f, nb, st);
@@ -1467,7 +1483,7 @@ struct StreamBuildDev {
     PropDev pd;
     int2* beams;
     float* vslot[2];
-    float2 *T, *W;
+    float2 *T, *R0, *W;
     float2* Sst[2];
 };
 
@@ -1478,6 +1494,7 @@ static void stream_build_carve(Carve& c, const prism_smatrix_desc* d, StreamBuil
     m.vslot[0] = c.take<float>((size_t)n * n);
     m.vslot[1] = c.take<float>((size_t)n * n);
     m.T = c.take<float2>((size_t)n * n);
+    m.R0 = c.take<float2>((size_t)n * n);
     m.W = c.take<float2>((size_t)NB * (n / 2) * wave_col_stride(n));
     m.Sst[0] = c.take<float2>((size_t)NB * d->ns * d->ns);
     m.Sst[1] = c.take<float2>((size_t)NB * d->ns * d->ns);
@@ -1534,7 +1551,13 @@ int prism_build_smatrix_streaming(const prism_smatrix_desc* d, const float* V_ho
         for (int s = 0; s < nsl; ++s) {
             rc = feed_slice(vr, g++, V_host, s, n, m.vslot, m.T, (float)d->sigma, st, h2d);
             if (rc) return rc;
-            HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, m.W, m.T, tb, bb, s == 0, nb, st); }));
+            if (s == 0) {
+                // the first slice's row spectrum, rebuilt per batch (the slice buffer is reused)
+                HIP_TRY(timed(PRISM_K_TRANSMISSION, st, [&] { return launch_row_spectrum(n, m.T, m.R0, tb, st); }));
+                HIP_TRY(timed(PRISM_K_FIRST, st, [&] { return launch_first_from_spectrum(n, m.W, m.R0, tb, bb, nb, st); }));
+            } else {
+                HIP_TRY(timed(PRISM_K_PASS_A, st, [&] { return launch_pass_a(n, m.W, m.T, tb, nb, st); }));
+            }
             HIP_TRY(timed(PRISM_K_PASS_B, st, [&] {
                 return launch_pass_b(n, s == nsl - 1 ? PASSB_LAST_S : PASSB_MID, m.W, tb, nullptr, nullptr, nullptr,
                                      nullptr, 0.0, 0.f, nb, st);

@@ -27,11 +27,18 @@ enum PassBMode { PASSB_MID = 0, PASSB_LAST_S = 1, PASSB_LAST_I = 2, PASSB_INIT =
 // T[s][y][x] = exp(i sigma V[s][y][x]) for count = n_slices*n*n pixels.
 hipError_t launch_transmission(const float* V, float2* T, int64_t count, float sigma, hipStream_t st);
 
-// Row pass: for each item and real-space row y, (optionally) inverse row
-// transform of the band, multiply by T[y][x], forward row transform, keep the
-// band.  first_pw: the input is the plane wave of the item's beam instead of W.
-hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb, const int2* beams,
-                         bool first_pw, int n_items, hipStream_t st);
+// Row pass: for each item and real-space row y, inverse row transform of the
+// band, multiply by T[y][x], forward row transform, keep the band.
+hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb, int n_items, hipStream_t st);
+
+// First row pass of plane-wave items, through the row spectrum of the first
+// slice's transmission: R[c][y] = sum_x T0[y][x] e^{-2 pi i c x/n} (complex64
+// [n][n], frequency-major), then W[item][j][y] = e^{2 pi i ky y/n}
+// R[(kx(j) - kx) mod n][y] for the item's beam (kx, ky) -- the band of the
+// row transform of the plane wave times T0.
+hipError_t launch_row_spectrum(int n, const float2* T0, float2* R, const PropTables& tb, hipStream_t st);
+hipError_t launch_first_from_spectrum(int n, float2* W, const float2* R, const PropTables& tb, const int2* beams,
+                                      int n_items, hipStream_t st);
 
 // Column pass (see PassBMode).  inten: band intensities [item][j][j'] for
 // PASSB_LAST_I.  For PASSB_INIT the spectrum is the aperture: |ky| <= ky_max[j],

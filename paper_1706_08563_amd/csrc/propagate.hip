@@ -167,10 +167,9 @@ template <int N>
 constexpr int pass_a_lds() { return RowCfgA<N>::TR * RowCfgA<N>::ROW + RowCfgA<N>::XO; }
 
 // One row-pass workgroup: logical block blk of a launch over n_items items.
-template <int N, bool FIRST>
+template <int N>
 __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float2* __restrict__ T,
-                                             const PropTables& tb, const int2* __restrict__ beams, int n_items,
-                                             int blk, float2* smem) {
+                                             const PropTables& tb, int n_items, int blk, float2* smem) {
     using C = RowCfgA<N>;
     using F = typename C::F;
     constexpr int L = C::L, E = C::E, LPT = C::LPT, TPW = C::TPW, TR = C::TR, ROW = C::ROW;
@@ -217,7 +216,7 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
         if constexpr (AFFINE) return sW[k * JSP];
         else return tile[yy0 * ROW + F::pad(j0 + JS * k)];
     };
-    if constexpr (!FIRST) {
+    {
         // all loads of the tile in flight before the first LDS store
         float2 ld[NLD];
 #pragma unroll
@@ -234,12 +233,6 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
     float2 btw[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) btw[i] = tb.band_tw[lt + LPT * i];
-    int kx = 0, ky = 0;
-    if constexpr (FIRST) {
-        int2 k = beams[item];
-        kx = k.x;
-        ky = k.y;
-    }
 
     for (int yy = tix; yy < TR; yy += TPW) {      // the same trip count for every wavefront
         const int y = y0 + yy;
@@ -253,29 +246,16 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
             for (int i = 0; i < E; ++i) trow[i] = Trow[lt + LPT * i];
         }
         float2 e[E], o[E];
-        if constexpr (FIRST) {
-            // plane wave e^{2 pi i (kx x + ky y)/N} at x = 2m, 2m+1 (exact integer phase)
 #pragma unroll
-            for (int i = 0; i < E; ++i) {
-                int m = lt + LPT * i;
-                int ph = (kx * 2 * m + ky * y) & (N - 1);
-                float2 w0 = tb.tw_full[ph];
-                float2 w1 = tb.tw_full[(ph + kx) & (N - 1)];
-                e[i] = make_float2(w0.x, -w0.y);
-                o[i] = make_float2(w1.x, -w1.y);
-            }
+        for (int i = 0; i < E; ++i) {
+            e[i] = row[F::pad(lt + LPT * i)];
+            o[i] = cmulc(e[i], btw[i]);
+        }
+        if constexpr (PRISM_PASSA_ILP) {
+            F::template run2<+1>(e, o, row, xodd + tix * F::LDS, tw, lt);
         } else {
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                e[i] = row[F::pad(lt + LPT * i)];
-                o[i] = cmulc(e[i], btw[i]);
-            }
-            if constexpr (PRISM_PASSA_ILP) {
-                F::template run2<+1>(e, o, row, xodd + tix * F::LDS, tw, lt);
-            } else {
-                F::template run<+1>(e, row, tw, lt);
-                F::template run<+1>(o, row, tw, lt);
-            }
+            F::template run<+1>(e, row, tw, lt);
+            F::template run<+1>(o, row, tw, lt);
         }
         if constexpr (N > PRISM_PASSA_TPREF) {
 #pragma unroll
@@ -306,38 +286,137 @@ __device__ __forceinline__ void pass_a_block(float2* __restrict__ W, const float
 template <int N>
 constexpr int pass_a_wpe() { return pass_span<N>() == 2 ? 2 : PRISM_PASSA_WPE; }
 
-template <int N, bool FIRST>
+template <int N>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass_a_wpe<N>()))) void k_pass_a(
-    float2* __restrict__ W, const float2* __restrict__ T, PropTables tb, const int2* __restrict__ beams,
-    int n_items) {
+    float2* __restrict__ W, const float2* __restrict__ T, PropTables tb, int n_items) {
     __shared__ float2 smem[pass_a_lds<N>()];
-    pass_a_block<N, FIRST>(W, T, tb, beams, n_items, blockIdx.x, smem);
+    pass_a_block<N>(W, T, tb, n_items, blockIdx.x, smem);
 }
 
 template <int N>
-static hipError_t pass_a_n(float2* W, const float2* T, const PropTables& tb, const int2* beams, bool first,
-                           int n_items, hipStream_t st) {
+static hipError_t pass_a_n(float2* W, const float2* T, const PropTables& tb, int n_items, hipStream_t st) {
     constexpr int TR = RowCfgA<N>::TR;
     dim3 grid((unsigned)((size_t)n_items * (N / TR)));
-    if (first)
-        hipLaunchKernelGGL((k_pass_a<N, true>), grid, dim3(WG), 0, st, W, T, tb, beams, n_items);
-    else
-        hipLaunchKernelGGL((k_pass_a<N, false>), grid, dim3(WG), 0, st, W, T, tb, beams, n_items);
+    hipLaunchKernelGGL((k_pass_a<N>), grid, dim3(WG), 0, st, W, T, tb, n_items);
     return hipGetLastError();
 }
 
-hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb, const int2* beams, bool first_pw,
-                         int n_items, hipStream_t st) {
+hipError_t launch_pass_a(int n, float2* W, const float2* T, const PropTables& tb, int n_items, hipStream_t st) {
     switch (n) {
-        case 64: return pass_a_n<64>(W, T, tb, beams, first_pw, n_items, st);
-        case 128: return pass_a_n<128>(W, T, tb, beams, first_pw, n_items, st);
-        case 256: return pass_a_n<256>(W, T, tb, beams, first_pw, n_items, st);
-        case 512: return pass_a_n<512>(W, T, tb, beams, first_pw, n_items, st);
-        case 1024: return pass_a_n<1024>(W, T, tb, beams, first_pw, n_items, st);
-        case 2048: return pass_a_n<2048>(W, T, tb, beams, first_pw, n_items, st);
+        case 64: return pass_a_n<64>(W, T, tb, n_items, st);
+        case 128: return pass_a_n<128>(W, T, tb, n_items, st);
+        case 256: return pass_a_n<256>(W, T, tb, n_items, st);
+        case 512: return pass_a_n<512>(W, T, tb, n_items, st);
+        case 1024: return pass_a_n<1024>(W, T, tb, n_items, st);
+        case 2048: return pass_a_n<2048>(W, T, tb, n_items, st);
     }
     return hipErrorInvalidValue;
 }
+
+// ------------------------------------------------------------ first slice --
+// A plane wave exp(2 pi i (kx x + ky y)/n) transmitted by the first slice and
+// row-transformed is the first slice's row spectrum shifted by kx and phased
+// by ky:
+//   sum_x e^{2 pi i (kx x + ky y)/n} T0[y][x] e^{-2 pi i k x/n} = e^{2 pi i ky y/n} R[(k - kx) mod n][y],
+//   R[c][y] = sum_x T0[y][x] e^{-2 pi i c x/n},
+// so the first row pass of every beam is a gather from one table R, built
+// once per call: an n-point transform per row, as two n/2-point transforms
+// of the even and odd frequencies (decimation in frequency).
+template <int N>
+__global__ __launch_bounds__(WG) void k_row_spectrum(const float2* __restrict__ T0, float2* __restrict__ R,
+                                                     PropTables tb) {
+    using F = Fft<N / 2>;
+    constexpr int L = N / 2, E = F::E, LPT = F::LPT, TPW = WG / LPT;
+    static_assert(N % TPW == 0, "whole rows per workgroup");
+    __shared__ float2 xch[TPW * F::LDS];
+    const int tid = threadIdx.x, tix = tid / LPT, lt = tid % LPT;
+    const int y = blockIdx.x * TPW + tix;
+    typename F::Twiddles tw;
+    tw.load(tb.tw_half, lt);
+    const float2* row = T0 + (size_t)y * N;
+    float2 a[E], b[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int x = lt + LPT * i;
+        const float2 u = row[x], v = row[x + L];
+        a[i] = cadd(u, v);                            // even frequencies 2c
+        b[i] = cmul(csub(u, v), tb.tw_full[x]);       // odd frequencies 2c + 1
+    }
+    float2* x = xch + tix * F::LDS;
+    F::template run<-1>(a, x, tw, lt);
+    F::template run<-1>(b, x, tw, lt);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int c = lt + LPT * i;
+        R[(size_t)(2 * c) * N + y] = a[i];
+        R[(size_t)(2 * c + 1) * N + y] = b[i];
+    }
+}
+
+// W[item][j][y] = e^{2 pi i ky y/n} R[(kx(j) - kx) mod n][y] for the item's
+// beam (kx, ky): one wavefront per band column, y contiguous in R and W.
+template <int N>
+__global__ __launch_bounds__(WG) void k_first_from_spectrum(float2* __restrict__ W, const float2* __restrict__ R,
+                                                            PropTables tb, const int2* __restrict__ beams,
+                                                            int n_items) {
+    constexpr int L = N / 2, CS = wave_col_stride(N);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = blockIdx.x * (WG / 64) + wave;    // item-major: item * L + j
+    const int item = col / L, j = col % L;
+    if (item >= n_items) return;
+    const int2 k = beams[item];
+    const int kxj = j < N / 4 ? j : j - L;
+    const float2* src = R + (size_t)((kxj - k.x) & (N - 1)) * N;
+    float2* dst = W + ((size_t)item * L + j) * CS;
+#pragma unroll 4
+    for (int y = lane; y < N; y += 64) {
+        const float2 w = tb.tw_full[(k.y * y) & (N - 1)];
+        dst[y] = cmulc(src[y], w);                    // R * conj(e^{-2 pi i ky y/n})
+    }
+}
+
+template <int N>
+static hipError_t row_spectrum_n(const float2* T0, float2* R, const PropTables& tb, hipStream_t st) {
+    constexpr int TPW = WG / Fft<N / 2>::LPT;
+    hipLaunchKernelGGL((k_row_spectrum<N>), dim3(N / TPW), dim3(WG), 0, st, T0, R, tb);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t first_n(float2* W, const float2* R, const PropTables& tb, const int2* beams, int n_items,
+                          hipStream_t st) {
+    constexpr int L = N / 2, CPB = WG / 64;
+    static_assert(L % CPB == 0, "whole workgroups per item");
+    dim3 grid((unsigned)((size_t)n_items * (L / CPB)));
+    hipLaunchKernelGGL((k_first_from_spectrum<N>), grid, dim3(WG), 0, st, W, R, tb, beams, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_spectrum(int n, const float2* T0, float2* R, const PropTables& tb, hipStream_t st) {
+    switch (n) {
+        case 64: return row_spectrum_n<64>(T0, R, tb, st);
+        case 128: return row_spectrum_n<128>(T0, R, tb, st);
+        case 256: return row_spectrum_n<256>(T0, R, tb, st);
+        case 512: return row_spectrum_n<512>(T0, R, tb, st);
+        case 1024: return row_spectrum_n<1024>(T0, R, tb, st);
+        case 2048: return row_spectrum_n<2048>(T0, R, tb, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_first_from_spectrum(int n, float2* W, const float2* R, const PropTables& tb, const int2* beams,
+                                      int n_items, hipStream_t st) {
+    switch (n) {
+        case 64: return first_n<64>(W, R, tb, beams, n_items, st);
+        case 128: return first_n<128>(W, R, tb, beams, n_items, st);
+        case 256: return first_n<256>(W, R, tb, beams, n_items, st);
+        case 512: return first_n<512>(W, R, tb, beams, n_items, st);
+        case 1024: return first_n<1024>(W, R, tb, beams, n_items, st);
+        case 2048: return first_n<2048>(W, R, tb, beams, n_items, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 
 // ------------------------------------------------------------------ pass B --
 // LDS (float2 slots) of one column-pass workgroup.

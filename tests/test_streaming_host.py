@@ -26,13 +26,13 @@ def test_streaming_build_workspace_is_small_and_scales_with_batch():
     w, g, d = _desc(P)
     n = g.n
     full = P.prism_streaming_build_workspace(d)
-    # two potential slices, one transmission slice, the band wave buffer and
-    # two S staging buffers of one batch, plus small tables
-    core = 2 * 4 * n * n + 8 * n * n + d.n_beams * (4 * n * n + 2 * 8 * d.ns * d.ns)
+    # two potential slices, one transmission slice and its row spectrum, the
+    # band wave buffer and two S staging buffers of one batch, plus small tables
+    core = 2 * 4 * n * n + 2 * 8 * n * n + d.n_beams * (4 * n * n + 2 * 8 * d.ns * d.ns)
     assert core <= full <= core + (1 << 20)
     _, _, d8 = _desc(P, beam_batch=8)
     small = P.prism_streaming_build_workspace(d8)
-    core8 = 2 * 4 * n * n + 8 * n * n + 8 * (4 * n * n + 2 * 8 * d.ns * d.ns)
+    core8 = 2 * 4 * n * n + 2 * 8 * n * n + 8 * (4 * n * n + 2 * 8 * d.ns * d.ns)
     assert core8 <= small <= core8 + (1 << 20)
     # with batching, the resident build still holds every slice's transmission,
     # the potential and the whole S-matrix; streaming holds none of them
