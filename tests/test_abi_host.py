@@ -258,3 +258,17 @@ def test_build_range_argument_checks():
     assert rc == P.PRISM_E_WORKSPACE
     # an empty range is accepted and does nothing
     assert P.lib.prism_build_smatrix_range(ct.byref(d), fake, fake, 5, 0, fake, d.build_ws_bytes, None) == P.PRISM_OK
+
+
+def test_timing_classes_match_the_header():
+    """Every timing class the binding names is readable, and the next index is
+    rejected (the header's PRISM_TIMING_CLASSES)."""
+    import paper_1706_08563_amd as P
+    hdr = open(os.path.join(ROOT, "include", "prism.h")).read()
+    n = int(re.search(r"#define PRISM_TIMING_CLASSES\s+(\d+)", hdr).group(1))
+    assert sorted(P.TIMING_CLASSES.values()) == list(range(n))
+    for name, cls in P.TIMING_CLASSES.items():
+        assert re.search(r"#define PRISM_K_%s\s+%d\b" % (name.upper(), cls), hdr), name
+        P.prism_timing_read(cls)
+    with pytest.raises(P.PrismError):
+        P.prism_timing_read(n)
