@@ -659,8 +659,8 @@ def main():
         return (wall_s, [a.elapsed_time(c) for a, b, c in ev], [a.elapsed_time(b) for a, b, c in ev],
                 [b.elapsed_time(c) for a, b, c in ev])
 
-    # headline: the library's default build streams (two overlapping beam
-    # halves up to 1024^2, one stream above)
+    # headline: the library's default build streams (four overlapping beam
+    # parts up to 1024^2, one stream above)
     log(f"timed {args.steps} steps")
     P.prism_set_build_streams(0)
     wall, step_ms, build_ms, synth_ms = run_steps(args.steps, False)
@@ -761,7 +761,7 @@ def main():
         "p99_ms": float(np.percentile(step_ms, 99)),
         "build_ms": float(np.median(build_ms)),
         "build_ms_one_stream": float(np.median(build_ms_1)),
-        "build_streams": 2 if n <= 1024 else 1,
+        "build_streams": 4 if n <= 1024 else 1,     # the library's default for this grid
         "synthesis_ms": float(np.median(synth_ms)),
         "probe_plan_host_s": plan_s,
         # whole steps that also plan the scan (window corners, work tiles,

@@ -183,9 +183,8 @@ int prism_build_smatrix_range(const prism_smatrix_desc* d, const float* V, void*
                               int32_t count, void* ws, size_t ws_bytes, void* stream);
 
 /* Streams used by prism_build_smatrix (process-wide), n in 1..4, or 0 (the
- * default) for a count chosen by grid size: 2 for n <= 1024, 1 above, where
- * the row and column passes of 1024-point transforms gain nothing from
- * running together.  Every beam batch is split into n parts, run on `stream` and on n - 1
+ * default) for a count chosen by grid size: 4 for n <= 1024, 1 above.  Every
+ * beam batch is split into n parts, run on `stream` and on n - 1
  * partner streams that the library creates once per caller stream (default
  * priority, kept until the process ends), each part one slice behind the
  * previous one, so that row and column passes of different beams run

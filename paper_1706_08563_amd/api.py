@@ -393,7 +393,7 @@ def multislice_outputs_streaming(grid: prism_grid, E0: float, alpha_max: float, 
 
 
 def prism_set_build_streams(n: int):
-    """Streams of the S-matrix build, 1-4, or 0 (the default) for 2 up to
+    """Streams of the S-matrix build, 1-4, or 0 (the default) for 4 up to
     1024^2 grids and 1 above: each beam batch is split into that many parts
     that overlap on the current stream and partner streams; 1 runs everything
     on the current stream."""

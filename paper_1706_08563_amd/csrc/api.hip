@@ -705,14 +705,14 @@ constexpr int kMaxBuildStreams = 4;
 #ifndef PRISM_FORK_STAGE
 #define PRISM_FORK_STAGE 1
 #endif
-// 0: by grid size.  Two streams up to n = 1024 (1245 beams at 1024^2: 266 ->
-// 259 ms per build); one above, where a row pass and a column pass of
-// 1024-point transforms compete for the same LDS (1245 beams at 2048^2:
-// 1.505 s on two streams against 1.494 s on one).
+// 0: by grid size.  Four streams up to n = 1024 (1245 beams at 1024^2 on 1,
+// 2, 3 and 4 streams: 262.4, 253.9, 251.0 and 249.5 ms per build), one above
+// (1245 beams at 2048^2: 1.419, 1.410, 1.418 and 1.426 s, no gain beyond the
+// spread between runs).
 std::atomic<int> g_build_streams{0};
 int build_streams_for(int n) {
     const int s = g_build_streams.load();
-    return s > 0 ? s : (n <= 1024 ? 2 : 1);
+    return s > 0 ? s : (n <= 1024 ? 4 : 1);
 }
 std::mutex g_partner_mu;
 std::map<hipStream_t, std::vector<hipStream_t>> g_partner;
