@@ -270,8 +270,9 @@ class GpuExecutor:
         # device memory left free beside every request's footprint (the HIP
         # runtime's own queues, scratch and events)
         self.reserve_bytes = reserve_bytes
-        # requests above this footprint return their cached blocks when done
-        self.release_bytes = 16 << 30
+        # device buffers (S-matrices, build workspaces) of finished requests,
+        # each with the event after which it is free (or None)
+        self.pool = []
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
 
@@ -318,29 +319,83 @@ class GpuExecutor:
         return int(foot)
 
     # -- build --
+    def _fits(self, need: int) -> bool:
+        """Whether `need` bytes can be allocated while the device keeps the
+        reserve free: blocks the caching allocator holds are reused first,
+        fresh device memory only for the rest."""
+        torch = self.torch
+        cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
+        return torch.cuda.mem_get_info()[0] - max(0, need - cached) >= self.reserve_bytes
+
+    def _take(self, nbytes: int):
+        """(buffer, event) from the pool: at least `nbytes` (and at most 1/8
+        more), free once `event` (if any) has completed; None when the pool
+        has none."""
+        best = None
+        for i, (buf, _) in enumerate(self.pool):
+            size = buf.numel()
+            if nbytes <= size <= nbytes + max(nbytes >> 3, 64 << 20):
+                if best is None or size < self.pool[best][0].numel():
+                    best = i
+        return None if best is None else self.pool.pop(best)
+
+    def _drop_pool(self):
+        self.pool.clear()
+        self.torch.cuda.empty_cache()
+
     def start(self, req: Request):
         """Allocate and issue the request's first build range; False when the
-        device does not have its footprint (plus the reserve) free.  The
-        scheduler's budget counts footprints only, while the caching
-        allocator keeps the blocks of finished requests: those are returned
-        to the device before the request is declared not to fit."""
+        device cannot hold its footprint (plus the reserve).  The scheduler's
+        budget counts footprints only.  The S-matrix and build workspace come
+        from a pool of the buffers of finished requests when one of the size
+        is there: device memory returned to the driver and allocated again is
+        cleared first, seconds for a large S-matrix (5.6 s for 168 GB) during
+        which the GPU runs out of queued work.  The pool is given back to the
+        device only when a request does not fit otherwise."""
         torch, api = self.torch, self.api
-        need = req.footprint + self.reserve_bytes
-        if torch.cuda.mem_get_info()[0] < need:
-            torch.cuda.empty_cache()
-            if torch.cuda.mem_get_info()[0] < need:
-                return False
         info = req.info
         d = info["desc"]
+        sizes = {"build_ws": d.build_ws_bytes, "S": d.n_beams * d.ns * d.ns * 8}
+        bufs, out = {}, None                          # name -> (buffer, event to wait for)
+        for attempt in (0, 1):
+            for k, nb in sizes.items():
+                if k not in bufs:
+                    b = self._take(nb)
+                    if b is not None:
+                        bufs[k] = b
+            if self._fits(req.footprint - sum(b.numel() for b, _ in bufs.values())):
+                try:
+                    for k, nb in sizes.items():
+                        if k not in bufs:
+                            bufs[k] = (torch.empty(nb, dtype=torch.uint8, device="cuda"), None)
+                    out = torch.empty((req.n_probes, info["n_bins"]), dtype=torch.float32, device="cuda")
+                except torch.cuda.OutOfMemoryError:
+                    out = None
+                else:
+                    if torch.cuda.mem_get_info()[0] >= self.reserve_bytes:
+                        break
+                    out = None
+            if attempt == 1:
+                # keep what it holds for its next start
+                self.pool.extend(bufs.values())
+                return False
+            # not enough device memory: return the pool's other buffers to the
+            # device and try once more
+            self._drop_pool()
         st = torch.cuda.Stream()
+        for _, ev in bufs.values():
+            if ev is not None:
+                st.wait_event(ev)                     # the buffer's previous user has finished with it
+        bufs = {k: b for k, (b, _) in bufs.items()}
         info["stream"] = st
+        info["bufs"] = bufs
+        info["build_ws"] = bufs["build_ws"]
+        info["S"] = bufs["S"][:sizes["S"]].view(torch.complex64).view(d.n_beams, d.ns, d.ns)
+        info["out"] = out
         pos, sp, species = req.sample() if callable(req.sample) else req.sample
         with torch.cuda.stream(st):
             info["plans"] = [api.prism_probe_plan_upload(d, c, req.dalpha) for c in info["chunks"]]
             info["V"] = api.prism_project_potential(pos, sp, species, info["grid"])
-            info["build_ws"] = torch.empty(d.build_ws_bytes, dtype=torch.uint8, device="cuda")
-            info["S"] = torch.empty((d.n_beams, d.ns, d.ns), dtype=torch.complex64, device="cuda")
-            info["out"] = torch.empty((req.n_probes, info["n_bins"]), dtype=torch.float32, device="cuda")
         info["range_beams"] = max(16, min(d.beam_batch or d.n_beams, self.range_pixels // (req.n * req.n)))
         info["next_beam"] = 0
         info["built_event"] = None
@@ -361,11 +416,15 @@ class GpuExecutor:
         info["next_beam"] = b0 + cnt
         info["built_event"] = ev
         if info["next_beam"] == d.n_beams:
-            # the last range is queued: the potential and the workspace are
-            # released once the stream has used them
-            for k in ("V", "build_ws"):
-                info[k].record_stream(st)
-                del info[k]
+            # the last range is queued: the potential is released once the
+            # stream has used it, the workspace goes to the pool behind an
+            # event of the stream
+            info["V"].record_stream(st)
+            del info["V"]
+            ws = info["bufs"].pop("build_ws")
+            ws.record_stream(st)                      # safe to free from the pool at any time
+            self.pool.append((ws, ev))
+            del info["build_ws"]
 
     def is_built(self, req: Request, may_issue: bool = True) -> bool:
         """True once every range has finished; issues the next range when the
@@ -430,10 +489,8 @@ class GpuExecutor:
         req.result = info["out"].cpu().numpy()
         for k in ("S", "out", "plans"):
             info.pop(k, None)
-        if req.footprint > self.release_bytes:
-            # return a large request's blocks to the device at once, so that
-            # the next large request finds them free rather than cached
-            self.torch.cuda.empty_cache()
+        # the S-matrix buffer (its syntheses have all finished) goes to the pool
+        self.pool.extend((b, None) for b in info.pop("bufs", {}).values())
 
     def chunks_left(self, req: Request):
         return range(req.chunks_issued, req.chunks_total)
