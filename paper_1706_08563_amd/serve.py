@@ -246,12 +246,68 @@ class Scheduler:
 
 
 # --------------------------------------------------------------- GPU side --
+class DeviceArena:
+    """Best-fit sub-allocator over one device buffer, for the large buffers
+    of the requests (S-matrices, build and synthesis workspaces).  Device
+    memory that the driver takes back and hands out again is cleared first,
+    seconds for the size of a large S-matrix (5.6 s for 168 GB) during which
+    the GPU runs out of queued work; carving every large buffer from one
+    allocation made once avoids that.  A released range keeps the events
+    after which it is free; whoever is given part of it waits for them."""
+
+    ALIGN = 1 << 21
+
+    def __init__(self, buf):
+        self.buf = buf
+        self.free = [[0, buf.numel(), []]]            # [offset, size, events], by offset
+
+    def alloc(self, nbytes: int):
+        """(offset, size, events to wait for) of a range of at least nbytes, or None."""
+        n = -(-max(int(nbytes), 1) // self.ALIGN) * self.ALIGN
+        best = None
+        for i, (_, size, _) in enumerate(self.free):
+            if size >= n and (best is None or size < self.free[best][1]):
+                best = i
+        if best is None:
+            return None
+        off, size, evs = self.free[best]
+        evs = [e for e in evs if not e.query()]
+        if size == n:
+            del self.free[best]
+        else:
+            self.free[best] = [off + n, size - n, list(evs)]
+        return off, n, evs
+
+    def release(self, off: int, n: int, event=None):
+        """Return a range; `event` (if any) completes when its last user is done."""
+        evs = [event] if event is not None else []
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        self.free.insert(i, [off, n, evs])
+        # coalesce with the following and the preceding free range
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            nxt = self.free.pop(i + 1)
+            self.free[i][1] += nxt[1]
+            self.free[i][2] += nxt[2]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            cur = self.free.pop(i)
+            self.free[i - 1][1] += cur[1]
+            self.free[i - 1][2] += cur[2]
+        for r in self.free:
+            r[2] = [e for e in r[2] if not e.query()]
+
+    @property
+    def free_bytes(self):
+        return sum(size for _, size, _ in self.free)
+
+
 class GpuExecutor:
     """Runs requests with libprism on the current HIP device."""
 
     def __init__(self, precision: int, probe_chunk_bytes: int = 1 << 30, build_ws_bytes: int = 16 << 30,
                  split_limit_bytes: int = 8 << 30, jobs_per_request: int = 4, range_pixels: int = 1 << 30,
-                 reserve_bytes: int = 8 << 30):
+                 reserve_bytes: int = 8 << 30, arena_bytes: int | None = None):
         import torch
 
         from . import api
@@ -270,9 +326,13 @@ class GpuExecutor:
         # device memory left free beside every request's footprint (the HIP
         # runtime's own queues, scratch and events)
         self.reserve_bytes = reserve_bytes
-        # device buffers (S-matrices, build workspaces) of finished requests,
-        # each with the event after which it is free (or None)
-        self.pool = []
+        # one allocation for the large buffers (DeviceArena), made at the
+        # first start: arena_bytes, or the free device memory less the
+        # reserve and arena_headroom for the smaller allocations (potentials,
+        # outputs, plans)
+        self.arena_bytes = arena_bytes
+        self.arena_headroom = 16 << 30
+        self.arena = None
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
 
@@ -327,70 +387,68 @@ class GpuExecutor:
         cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
         return torch.cuda.mem_get_info()[0] - max(0, need - cached) >= self.reserve_bytes
 
-    def _take(self, nbytes: int):
-        """(buffer, event) from the pool: at least `nbytes` (and at most 1/8
-        more), free once `event` (if any) has completed; None when the pool
-        has none."""
-        best = None
-        for i, (buf, _) in enumerate(self.pool):
-            size = buf.numel()
-            if nbytes <= size <= nbytes + max(nbytes >> 3, 64 << 20):
-                if best is None or size < self.pool[best][0].numel():
-                    best = i
-        return None if best is None else self.pool.pop(best)
+    def _alloc(self, nbytes: int, stream):
+        """A uint8 device buffer of nbytes usable on `stream` and its handle:
+        from the arena when it has room, else from the caching allocator when
+        the device can hold it (None otherwise)."""
+        torch = self.torch
+        if self.arena is None:
+            size = self.arena_bytes
+            if size is None:
+                size = torch.cuda.mem_get_info()[0] - self.reserve_bytes - self.arena_headroom
+            size = (int(size) // DeviceArena.ALIGN) * DeviceArena.ALIGN
+            self.arena = DeviceArena(torch.empty(max(size, DeviceArena.ALIGN), dtype=torch.uint8, device="cuda"))
+        r = self.arena.alloc(nbytes)
+        if r is not None:
+            off, n, evs = r
+            for e in evs:
+                stream.wait_event(e)                  # the range's previous users have finished
+            return self.arena.buf[off:off + nbytes], ("arena", off, n)
+        if not self._fits(nbytes):
+            torch.cuda.empty_cache()
+            if not self._fits(nbytes):
+                return None
+        try:
+            t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        except torch.cuda.OutOfMemoryError:
+            return None
+        return t, ("torch", t)
 
-    def _drop_pool(self):
-        self.pool.clear()
-        self.torch.cuda.empty_cache()
+    def _release(self, handle, event=None, stream=None):
+        if handle[0] == "arena":
+            self.arena.release(handle[1], handle[2], event)
+        elif stream is not None:
+            handle[1].record_stream(stream)           # the caching allocator waits for the stream
 
     def start(self, req: Request):
         """Allocate and issue the request's first build range; False when the
         device cannot hold its footprint (plus the reserve).  The scheduler's
-        budget counts footprints only.  The S-matrix and build workspace come
-        from a pool of the buffers of finished requests when one of the size
-        is there: device memory returned to the driver and allocated again is
-        cleared first, seconds for a large S-matrix (5.6 s for 168 GB) during
-        which the GPU runs out of queued work.  The pool is given back to the
-        device only when a request does not fit otherwise."""
+        budget counts footprints only.  The S-matrix and the build workspace
+        come from the arena (DeviceArena), else from the caching allocator."""
         torch, api = self.torch, self.api
         info = req.info
         d = info["desc"]
-        sizes = {"build_ws": d.build_ws_bytes, "S": d.n_beams * d.ns * d.ns * 8}
-        bufs, out = {}, None                          # name -> (buffer, event to wait for)
-        for attempt in (0, 1):
-            for k, nb in sizes.items():
-                if k not in bufs:
-                    b = self._take(nb)
-                    if b is not None:
-                        bufs[k] = b
-            if self._fits(req.footprint - sum(b.numel() for b, _ in bufs.values())):
-                try:
-                    for k, nb in sizes.items():
-                        if k not in bufs:
-                            bufs[k] = (torch.empty(nb, dtype=torch.uint8, device="cuda"), None)
-                    out = torch.empty((req.n_probes, info["n_bins"]), dtype=torch.float32, device="cuda")
-                except torch.cuda.OutOfMemoryError:
-                    out = None
-                else:
-                    if torch.cuda.mem_get_info()[0] >= self.reserve_bytes:
-                        break
-                    out = None
-            if attempt == 1:
-                # keep what it holds for its next start
-                self.pool.extend(bufs.values())
-                return False
-            # not enough device memory: return the pool's other buffers to the
-            # device and try once more
-            self._drop_pool()
         st = torch.cuda.Stream()
-        for _, ev in bufs.values():
-            if ev is not None:
-                st.wait_event(ev)                     # the buffer's previous user has finished with it
-        bufs = {k: b for k, (b, _) in bufs.items()}
+        s_bytes = d.n_beams * d.ns * d.ns * 8
+        got = []
+        for nb in (d.build_ws_bytes, s_bytes):
+            r = self._alloc(nb, st)
+            if r is None:
+                for _, h in got:
+                    self._release(h)
+                return False
+            got.append(r)
+        (ws, ws_h), (sbuf, s_h) = got
+        try:
+            out = torch.empty((req.n_probes, info["n_bins"]), dtype=torch.float32, device="cuda")
+        except torch.cuda.OutOfMemoryError:
+            for _, h in got:
+                self._release(h)
+            return False
         info["stream"] = st
-        info["bufs"] = bufs
-        info["build_ws"] = bufs["build_ws"]
-        info["S"] = bufs["S"][:sizes["S"]].view(torch.complex64).view(d.n_beams, d.ns, d.ns)
+        info["handles"] = {"build_ws": ws_h, "S": s_h}
+        info["build_ws"] = ws
+        info["S"] = sbuf.view(torch.complex64).view(d.n_beams, d.ns, d.ns)
         info["out"] = out
         pos, sp, species = req.sample() if callable(req.sample) else req.sample
         with torch.cuda.stream(st):
@@ -416,14 +474,11 @@ class GpuExecutor:
         info["next_beam"] = b0 + cnt
         info["built_event"] = ev
         if info["next_beam"] == d.n_beams:
-            # the last range is queued: the potential is released once the
-            # stream has used it, the workspace goes to the pool behind an
-            # event of the stream
+            # the last range is queued: the potential and the workspace are
+            # released, free once the stream has used them
             info["V"].record_stream(st)
             del info["V"]
-            ws = info["bufs"].pop("build_ws")
-            ws.record_stream(st)                      # safe to free from the pool at any time
-            self.pool.append((ws, ev))
+            self._release(info["handles"].pop("build_ws"), ev, st)
             del info["build_ws"]
 
     def is_built(self, req: Request, may_issue: bool = True) -> bool:
@@ -459,19 +514,26 @@ class GpuExecutor:
             (single if info.get("beam_chunk") else items).append((it, info.get("beam_chunk")))
             req.chunks_issued += 1
         keep = []
+
+        def workspace(nbytes):
+            r = self._alloc(max(int(nbytes), 1), self.synth_stream)
+            if r is None:                             # as the caching allocator alone would
+                t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+                r = (t, ("torch", t))
+            keep.append(r[1])
+            return r[0]
+
         with torch.cuda.stream(self.synth_stream):
             if items:
                 its = [it for it, _ in items]
-                ws = torch.empty(max(api.prism_probe_batch_workspace(its), 1), dtype=torch.uint8, device="cuda")
+                ws = workspace(api.prism_probe_batch_workspace(its))
                 api.prism_probe_outputs_batched(its, self.precision, ws=ws)
-                keep.append(ws)
             if single:
                 # one workspace serves every beam-chunked item (same stream, in order)
                 need = max(api.prism_probe_chunked_workspace(d, plan, bc) for (d, S, plan, out), bc in single)
-                ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+                ws = workspace(need)
                 for (d, S, plan, out), bc in single:
                     api.prism_probe_outputs_chunked(d, S, plan, self.precision, bc, ws=ws, out=out)
-                keep.append(ws)
             ev = torch.cuda.Event()
             ev.record(self.synth_stream)
         self.inflight.append((ev, list(batch), keep))
@@ -480,7 +542,9 @@ class GpuExecutor:
         """Batches whose synthesis completed (in issue order)."""
         done = []
         while self.inflight and self.inflight[0][0].query():
-            ev, batch, ws = self.inflight.pop(0)
+            ev, batch, handles = self.inflight.pop(0)
+            for h in handles:
+                self._release(h)                      # its synthesis has finished
             done.append(batch)
         return done
 
@@ -489,8 +553,9 @@ class GpuExecutor:
         req.result = info["out"].cpu().numpy()
         for k in ("S", "out", "plans"):
             info.pop(k, None)
-        # the S-matrix buffer (its syntheses have all finished) goes to the pool
-        self.pool.extend((b, None) for b in info.pop("bufs", {}).values())
+        # the S-matrix's range (its syntheses have all finished)
+        for h in info.pop("handles", {}).values():
+            self._release(h)
 
     def chunks_left(self, req: Request):
         return range(req.chunks_issued, req.chunks_total)

@@ -278,3 +278,49 @@ def test_build_pacing_in_the_serving_loop():
     big_paced, small_paced = run(build_ratio=4.0, build_hold=1.0)
     assert small_paced < small_free
     assert big_paced >= big_free
+
+
+class _Buf:
+    def __init__(self, n):
+        self.n = n
+
+    def numel(self):
+        return self.n
+
+
+class _Ev:
+    def __init__(self, done=False):
+        self.done = done
+
+    def query(self):
+        return self.done
+
+
+def test_device_arena_best_fit_coalescing_and_events():
+    """The arena gives disjoint aligned ranges, picks the smallest free range
+    that fits, merges neighbours on release and hands the pending events of a
+    released range to its next owner (completed events are dropped)."""
+    from paper_1706_08563_amd.serve import DeviceArena
+    A = DeviceArena.ALIGN
+    ar = DeviceArena(_Buf(10 * A))
+    a = ar.alloc(3 * A)
+    b = ar.alloc(1)                                  # rounded up to one alignment unit
+    c = ar.alloc(2 * A)
+    assert [x[:2] for x in (a, b, c)] == [(0, 3 * A), (3 * A, A), (4 * A, 2 * A)]
+    assert ar.alloc(5 * A) is None and ar.free_bytes == 4 * A
+    pending, finished = _Ev(False), _Ev(True)
+    ar.release(b[0], b[1], pending)                  # a 1-unit hole at 3A
+    ar.release(a[0], a[1], finished)                 # merges with it: [0, 4A)
+    assert ar.free[0][:2] == [0, 4 * A] and ar.free[0][2] == [pending]
+    d = ar.alloc(4 * A)                              # two free ranges of 4A: the first is taken
+    assert d[:2] == (0, 4 * A) and d[2] == [pending]
+    e = ar.alloc(A)                                  # from the tail [6A, 10A)
+    assert e[:2] == (6 * A, A) and e[2] == []
+    for r in (c, d, e):
+        ar.release(r[0], r[1])
+    assert len(ar.free) == 1 and ar.free[0][:2] == [0, 10 * A]
+    # best fit prefers the smaller of two holes
+    x, y, z = ar.alloc(2 * A), ar.alloc(A), ar.alloc(3 * A)
+    ar.release(x[0], x[1])
+    ar.release(z[0], z[1])                           # holes: 2A at 0 and 7A from 3A (merged with the tail)
+    assert ar.alloc(2 * A)[:2] == (0, 2 * A)
