@@ -305,6 +305,8 @@ def serving_report(args, n_requests, grids, loads, seed=4, quiet=False, capacity
         torch.cuda.empty_cache()
         log(f"[{tag}] serving {len(reqs)} requests at {rate:.3f}/s, budget {cap / 1e9:.1f} GB")
         ex = SV.GpuExecutor(prec, jobs_per_request=4)
+        ex.reserve_arena()                 # the server's device arena, allocated before the stream starts
+        torch.cuda.synchronize()
         # batch cost: 2.5e12 complex multiply-adds, ~50 ms of split-BF16 contraction
         sched = SV.Scheduler(cap, max_building=4, max_jobs=24, jobs_per_request=4, batch_cost=2.5e12)
         t0 = time.perf_counter()

@@ -331,7 +331,7 @@ class GpuExecutor:
         # reserve and arena_headroom for the smaller allocations (potentials,
         # outputs, plans)
         self.arena_bytes = arena_bytes
-        self.arena_headroom = 16 << 30
+        self.arena_headroom = 24 << 30
         self.arena = None
         self.synth_stream = torch.cuda.Stream()
         self.inflight = []              # (event, [(req, chunk)], ws)
@@ -387,10 +387,9 @@ class GpuExecutor:
         cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
         return torch.cuda.mem_get_info()[0] - max(0, need - cached) >= self.reserve_bytes
 
-    def _alloc(self, nbytes: int, stream):
-        """A uint8 device buffer of nbytes usable on `stream` and its handle:
-        from the arena when it has room, else from the caching allocator when
-        the device can hold it (None otherwise)."""
+    def reserve_arena(self):
+        """Allocate the arena now (else at the first request): a server's
+        start-up cost, seconds when the memory was in use before."""
         torch = self.torch
         if self.arena is None:
             size = self.arena_bytes
@@ -398,7 +397,14 @@ class GpuExecutor:
                 size = torch.cuda.mem_get_info()[0] - self.reserve_bytes - self.arena_headroom
             size = (int(size) // DeviceArena.ALIGN) * DeviceArena.ALIGN
             self.arena = DeviceArena(torch.empty(max(size, DeviceArena.ALIGN), dtype=torch.uint8, device="cuda"))
-        r = self.arena.alloc(nbytes)
+        return self.arena
+
+    def _alloc(self, nbytes: int, stream):
+        """A uint8 device buffer of nbytes usable on `stream` and its handle:
+        from the arena when it has room, else from the caching allocator when
+        the device can hold it (None otherwise)."""
+        torch = self.torch
+        r = self.reserve_arena().alloc(nbytes)
         if r is not None:
             off, n, evs = r
             for e in evs:
