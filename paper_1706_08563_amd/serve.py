@@ -14,6 +14,9 @@ scan each) arrive over time.  The loop
   `prism_build_smatrix_range`), the next range only once the previous one
   has finished, so other requests' work never queues behind a whole large
   build on a shared hardware queue;
+* carves the large device buffers (S-matrices, workspaces) from one arena
+  allocated once, since device memory returned to the driver and allocated
+  again is cleared first (seconds for a large S-matrix);
 * keeps every built S-matrix resident until its probes are done, and
   synthesises probes of all built requests together: each scheduling step
   issues one batched synthesis (prism_probe_outputs_batched) over up to
@@ -326,15 +329,15 @@ class GpuExecutor:
         # device memory left free beside every request's footprint (the HIP
         # runtime's own queues, scratch and events)
         self.reserve_bytes = reserve_bytes
-        # one allocation for the large buffers (DeviceArena), made at the
-        # first start: arena_bytes, or the free device memory less the
-        # reserve and arena_headroom for the smaller allocations (potentials,
-        # outputs, plans)
+        # one allocation for the large buffers (DeviceArena), made by
+        # reserve_arena() or at the first start: arena_bytes, or the free
+        # device memory less the reserve and arena_headroom for the smaller
+        # allocations (potentials, outputs, plans)
         self.arena_bytes = arena_bytes
         self.arena_headroom = 24 << 30
         self.arena = None
         self.synth_stream = torch.cuda.Stream()
-        self.inflight = []              # (event, [(req, chunk)], ws)
+        self.inflight = []              # (event, [(req, chunk)], workspace handles)
 
     # -- planning (host) --
     def plan(self, req: Request):
