@@ -324,3 +324,36 @@ def test_device_arena_best_fit_coalescing_and_events():
     ar.release(x[0], x[1])
     ar.release(z[0], z[1])                           # holes: 2A at 0 and 7A from 3A (merged with the tail)
     assert ar.alloc(2 * A)[:2] == (0, 2 * A)
+
+
+def test_device_arena_random_alloc_release_never_overlaps():
+    """A seeded random sequence of allocations and releases: live ranges
+    never overlap, stay inside the buffer, and live + free bytes always equal
+    the buffer; after releasing everything one free range remains."""
+    import random
+    from paper_1706_08563_amd.serve import DeviceArena
+    A = DeviceArena.ALIGN
+    cap = 64 * A
+    ar = DeviceArena(_Buf(cap))
+    rng = random.Random(7)
+    live = []
+    for _ in range(2000):
+        if live and (rng.random() < 0.45 or ar.free_bytes < A):
+            off, n, _ = live.pop(rng.randrange(len(live)))
+            ar.release(off, n, _Ev(rng.random() < 0.5))
+        else:
+            r = ar.alloc(rng.randint(1, 9 * A))
+            if r is not None:
+                off, n, evs = r
+                assert off % A == 0 and n % A == 0 and 0 <= off and off + n <= cap
+                assert all(not e.query() for e in evs)
+                for o, m, _ in live:
+                    assert off + n <= o or o + m <= off
+                live.append(r)
+        assert sum(n for _, n, _ in live) + ar.free_bytes == cap
+        offs = [f[0] for f in ar.free]
+        assert offs == sorted(offs)
+        assert all(a[0] + a[1] < b[0] for a, b in zip(ar.free, ar.free[1:]))   # neighbours merged
+    for off, n, _ in live:
+        ar.release(off, n)
+    assert len(ar.free) == 1 and ar.free[0][:2] == [0, cap]
