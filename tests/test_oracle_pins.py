@@ -695,3 +695,21 @@ def test_virtual_detector_annular_map_equals_default():
     nmap = O.bin_map(lam, n, L, O.alpha_aa(lam, n, L), 1e-3, nb)
     assert np.array_equal(O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy, detector_map=nmap, n_bins=nb),
                           O.multislice_outputs(V, L, w.dz, lam, sig, w.alpha_max, xy))
+
+
+def test_first_slice_is_the_shifted_row_spectrum():
+    """The identity the first row pass of the GPU build rests on (shift
+    theorem, Eqs. 1-2 with a plane-wave input): the row transform of a plane
+    wave e^{2 pi i (kx x + ky y)/n} times a transmission T equals the row
+    transform of T shifted by kx and phased by e^{2 pi i ky y/n}."""
+    rng = np.random.default_rng(5)
+    n = 64
+    T = np.exp(1j * rng.uniform(0, 2, size=(n, n)))
+    y, x = np.mgrid[0:n, 0:n]
+    R = np.fft.fft(T, axis=1)
+    for kx, ky in ((0, 0), (3, -5), (-7, 2), (31, -32)):
+        pw = np.exp(2j * np.pi * (kx * x + ky * y) / n)
+        lhs = np.fft.fft(pw * T, axis=1)
+        k = np.arange(n)
+        rhs = np.exp(2j * np.pi * ky * np.arange(n) / n)[:, None] * R[:, (k - kx) % n]
+        assert np.max(np.abs(lhs - rhs)) < 1e-10 * np.max(np.abs(lhs))
